@@ -1,0 +1,268 @@
+"""Seeded synthetic inputs for the ultra-relativistic lattice Boltzmann update.
+
+This module holds input recipes only: initial fields (energy density eps,
+velocity u, particle density n), obstacle masks, boundary conditions and run
+parameters.  It contains none of the lattice update's arithmetic; the same
+arrays are handed to the HIP library and to the CPU oracle.
+
+Lattice units: ambient temperature T = 1, n = 1, eps = 3 T^4 = 3 (eps = 3p,
+p = nT), nu = 27^(1/4) unless stated.  Seeds are 1302112500 + k for
+workload k.  The five workloads are synthetic stand-ins shaped like the
+paper's Riemann-problem and shock-cloud experiments (Sec. III); no dataset is
+involved.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+NU_DEFAULT = 27.0 ** 0.25
+SEED_BASE = 1302112500
+
+BC_PERIODIC, BC_FIXED, BC_OUTFLOW = 0, 1, 2
+FP64, MIXED = 0, 1
+COLL_IMPLICIT, COLL_EULER = 0, 1
+TAU_UNIFORM, TAU_ETA_OVER_S = 0, 1
+
+
+@dataclass
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    steps: int
+    precision: int = FP64
+    collision: int = COLL_IMPLICIT
+    tau_mode: int = TAU_ETA_OVER_S
+    tau: float = 1.0
+    eta_over_s: float = 0.0
+    alpha: float = 0.0
+    with_density: bool = False
+    nu: float = NU_DEFAULT
+    dt: float = 0.25
+    bc: List[int] = field(default_factory=lambda: [BC_PERIODIC] * 6)
+    face_states: List[List[float]] = field(default_factory=lambda: [[3.0, 0.0, 0.0, 0.0, 1.0]] * 6)
+    guard_umax: float = 0.0
+    guard_efloor: float = 1e-10
+    eps: Optional[np.ndarray] = None
+    ux: Optional[np.ndarray] = None
+    uy: Optional[np.ndarray] = None
+    uz: Optional[np.ndarray] = None
+    n: Optional[np.ndarray] = None
+    obstacle: Optional[np.ndarray] = None
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def ncell(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def fields(self):
+        return self.eps, self.ux, self.uy, self.uz, self.n
+
+    def copy_with(self, **kw) -> "Workload":
+        d = dict(self.__dict__)
+        d.update(kw)
+        return Workload(**d)
+
+
+def _zeros(shape):
+    return np.zeros(shape, dtype=np.float64)
+
+
+def shock_tube_1d(nx=1000, steps=500, T_left=2.0, T_right=1.0, eta_over_s=0.1,
+                  alpha=0.0, with_density=False, precision=FP64, collision=COLL_IMPLICIT,
+                  dt=0.25, nu=NU_DEFAULT, bc_ends=BC_FIXED) -> Workload:
+    """Workload 1: quasi-1D viscous shock tube, left half T=2, right half T=1
+    (energy ratio 16), fluid at rest, fixed-state ends, periodic transverse."""
+    x = np.arange(nx)
+    T = np.where(x < nx // 2, T_left, T_right)
+    eps = 3.0 * T ** 4
+    n = T ** 3
+    shape = (1, 1, nx)
+    w = Workload("shock_tube_1d", nx, 1, 1, steps, precision=precision, collision=collision,
+                 tau_mode=TAU_ETA_OVER_S, eta_over_s=eta_over_s, alpha=alpha,
+                 with_density=with_density, nu=nu, dt=dt,
+                 bc=[bc_ends, bc_ends] + [BC_PERIODIC] * 4,
+                 face_states=[[3.0 * T_left ** 4, 0, 0, 0, T_left ** 3],
+                              [3.0 * T_right ** 4, 0, 0, 0, T_right ** 3]] + [[3.0, 0, 0, 0, 1.0]] * 4)
+    w.eps = eps.reshape(shape)
+    w.ux, w.uy, w.uz = _zeros(shape), _zeros(shape), _zeros(shape)
+    w.n = n.reshape(shape)
+    return w
+
+
+def colliding_slabs_1d(nx=8192, steps=4000, gamma=10.0, eta_over_s=0.05, zeta_over_eta=0.5,
+                       precision=FP64, seed=SEED_BASE + 2, nu=NU_DEFAULT, dt=0.25,
+                       guard_umax=0.9999) -> Workload:
+    """Workload 2: two slabs with opposite velocities at Lorentz factor gamma,
+    eps = 3, n = 1 (1 + 0.01 U(-1,1)) per cell, inflow (fixed-state) ends.
+    The bulk constant alpha follows from zeta/eta through the paper's
+    eta_b = 4 p alpha nu^6 / 27 with eta = (eta/s) s, s = 4n at the ambient
+    state (T = n = p = 1)."""
+    rng = np.random.default_rng(seed)
+    beta = math.sqrt(1.0 - 1.0 / gamma ** 2)
+    x = np.arange(nx)
+    ux = np.where(x < nx // 2, beta, -beta)
+    n = 1.0 + 0.01 * rng.uniform(-1.0, 1.0, nx)
+    eta = eta_over_s * 4.0
+    alpha = zeta_over_eta * eta * 27.0 / (4.0 * 1.0 * nu ** 6)
+    shape = (1, 1, nx)
+    w = Workload("colliding_slabs_1d", nx, 1, 1, steps, precision=precision,
+                 tau_mode=TAU_ETA_OVER_S, eta_over_s=eta_over_s, alpha=alpha,
+                 with_density=True, nu=nu, dt=dt,
+                 bc=[BC_FIXED, BC_FIXED] + [BC_PERIODIC] * 4,
+                 face_states=[[3.0, beta, 0, 0, 1.0], [3.0, -beta, 0, 0, 1.0]] + [[3.0, 0, 0, 0, 1.0]] * 4,
+                 guard_umax=guard_umax)
+    w.eps = np.full(shape, 3.0)
+    w.ux = ux.reshape(shape).astype(np.float64)
+    w.uy, w.uz = _zeros(shape), _zeros(shape)
+    w.n = n.reshape(shape)
+    return w
+
+
+def planar_shock_state(gamma_s: float, p_a=1.0, n_a=1.0):
+    """State behind a planar shock moving into fluid at rest with eps = 3p:
+    post-shock speed u with gamma_s, pressure from the jump condition
+    u^2 (3 p_a + p)(3 p + p_a) = 3 (p - p_a)^2, front speed from energy
+    conservation and density from the particle-flux condition."""
+    u = math.sqrt(1.0 - 1.0 / gamma_s ** 2)
+    a = 3.0 - 3.0 * u * u
+    b = -(6.0 * p_a + 10.0 * u * u * p_a)
+    c = (3.0 - 3.0 * u * u) * p_a * p_a
+    p = (-b + math.sqrt(b * b - 4 * a * c)) / (2 * a)
+    g2 = gamma_s ** 2
+    T00b, T0xb = 4 * p * g2 - p, 4 * p * g2 * u
+    Vs = T0xb / (T00b - 3.0 * p_a)
+    n = n_a * Vs / (gamma_s * (Vs - u))
+    return p, u, Vs, n
+
+
+def shock_cloud_2d(nx=2048, ny=1024, steps=20000, gamma_s=3.0, cloud_radius=96.0,
+                   shock_x=256, cloud_center=(768.0, 512.0), eta_over_s=0.01, alpha=0.2,
+                   precision=MIXED, seed=SEED_BASE + 3, nu=NU_DEFAULT, dt=0.15,
+                   guard_umax=0.999) -> Workload:
+    """Workload 3: planar shock (post-shock gamma = 3) moving towards a
+    circular cloud of radius 96 cells whose edge carries seeded Fourier modes
+    1..16 of amplitude 2%.  The cloud is an obstacle held at the equilibrium
+    of (eps_a, 10 n_a, u = 0) (the paper's shock-cloud mechanism, Sec. III).
+    Left face: fixed inflow of the shocked state; other faces: outflow.
+    Geometry scales with (nx, ny) relative to 2048 x 1024.  The
+    admissibility guard is on by default: without it the scheme as read
+    leaves the admissible set at the shock front within a few steps."""
+    rng = np.random.default_rng(seed)
+    sx, sy = nx / 2048.0, ny / 1024.0
+    p_s, u_s, _, n_s = planar_shock_state(gamma_s)
+    shape = (1, ny, nx)
+    X, Y = np.meshgrid(np.arange(nx) + 0.5, np.arange(ny) + 0.5)
+    eps = np.where(X < shock_x * sx, 3.0 * p_s, 3.0)
+    ux = np.where(X < shock_x * sx, u_s, 0.0)
+    n = np.where(X < shock_x * sx, n_s, 1.0)
+    am = rng.uniform(-1, 1, 16)
+    bm = rng.uniform(-1, 1, 16)
+    cx, cy = cloud_center[0] * sx, cloud_center[1] * sy
+    theta = np.arctan2(Y - cy, X - cx)
+    m = np.arange(1, 17)
+    rho = (am[None, None, :] * np.cos(m * theta[..., None]) +
+           bm[None, None, :] * np.sin(m * theta[..., None])).sum(-1)
+    tt = np.linspace(-math.pi, math.pi, 4097)
+    rho_max = np.abs((am[None, :] * np.cos(m * tt[:, None]) + bm[None, :] * np.sin(m * tt[:, None])).sum(-1)).max()
+    R = cloud_radius * min(sx, sy) * (1.0 + 0.02 * rho / rho_max)
+    cloud = np.hypot(X - cx, Y - cy) < R
+    eps = np.where(cloud, 3.0, eps)
+    n = np.where(cloud, 10.0, n)
+    ux = np.where(cloud, 0.0, ux)
+    w = Workload("shock_cloud_2d", nx, ny, 1, steps, precision=precision,
+                 tau_mode=TAU_ETA_OVER_S, eta_over_s=eta_over_s, alpha=alpha,
+                 with_density=True, nu=nu, dt=dt,
+                 bc=[BC_FIXED, BC_OUTFLOW, BC_OUTFLOW, BC_OUTFLOW, BC_PERIODIC, BC_PERIODIC],
+                 face_states=[[3.0 * p_s, u_s, 0, 0, n_s]] + [[3.0, 0, 0, 0, 1.0]] * 5,
+                 guard_umax=guard_umax)
+    w.eps = eps.reshape(shape)
+    w.ux = ux.reshape(shape)
+    w.uy, w.uz = _zeros(shape), _zeros(shape)
+    w.n = n.reshape(shape)
+    w.obstacle = cloud.reshape(shape).astype(np.uint8)
+    return w
+
+
+def blast_wave_3d(n=384, steps=2000, radius=32.0, energy_ratio=1e3, eta_over_s=0.02,
+                  alpha=0.2, precision=MIXED, seed=SEED_BASE + 5, nu=NU_DEFAULT,
+                  dt=0.15, guard_umax=0.999) -> Workload:
+    """Workload 5: periodic cube with an overpressure sphere of radius 32
+    cells (energy ratio 1e3) at the centre of a medium with seeded 1%
+    log-normal density fluctuations n = exp(0.01 g - 0.5e-4), g ~ N(0,1).
+    The radius scales with n / 384.  The admissibility guard is on by
+    default (the density distribution turns inadmissible at the blast front
+    within a few tens of steps without it)."""
+    rng = np.random.default_rng(seed)
+    shape = (n, n, n)
+    g = rng.standard_normal(shape, dtype=np.float64)
+    dens = np.exp(0.01 * g - 0.5e-4)
+    del g
+    c = n / 2.0
+    r = radius * n / 384.0
+    ax = np.arange(n) + 0.5 - c
+    d2 = ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2
+    eps = np.where(d2 < r * r, 3.0 * energy_ratio, 3.0)
+    del d2
+    w = Workload("blast_wave_3d", n, n, n, steps, precision=precision,
+                 tau_mode=TAU_ETA_OVER_S, eta_over_s=eta_over_s, alpha=alpha,
+                 with_density=True, nu=nu, dt=dt, bc=[BC_PERIODIC] * 6,
+                 guard_umax=guard_umax)
+    w.eps = eps
+    w.ux, w.uy, w.uz = _zeros(shape), _zeros(shape), _zeros(shape)
+    w.n = dens
+    return w
+
+
+def uniform_state(nx, ny, nz, eps=3.0, u=(0.0, 0.0, 0.0), n=1.0, **kw) -> Workload:
+    """A uniform state (a fixed point of the update under periodic boundaries)."""
+    shape = (nz, ny, nx)
+    w = Workload("uniform", nx, ny, nz, kw.pop("steps", 10), **kw)
+    w.eps = np.full(shape, float(eps))
+    w.ux, w.uy, w.uz = (np.full(shape, float(v)) for v in u)
+    w.n = np.full(shape, float(n))
+    return w
+
+
+def random_smooth_state(nx, ny, nz, seed, amp_eps=0.3, umax=0.3, **kw) -> Workload:
+    """Seeded smooth random fields (a few Fourier modes) for parity tests."""
+    rng = np.random.default_rng(seed)
+    shape = (nz, ny, nx)
+    Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+
+    def field_():
+        s = np.zeros(shape)
+        for _ in range(4):
+            kx, ky, kz = rng.integers(0, 3, 3)
+            ph = rng.uniform(0, 2 * math.pi)
+            s += rng.uniform(-1, 1) * np.cos(2 * math.pi * (kx * X / nx + ky * Y / ny + kz * Z / nz) + ph)
+        return s / 4.0
+
+    w = Workload("random_smooth", nx, ny, nz, kw.pop("steps", 10), **kw)
+    w.eps = 3.0 * np.exp(amp_eps * field_())
+    w.ux = umax * field_()
+    w.uy = umax * field_() if ny > 1 else np.zeros(shape)
+    w.uz = umax * field_() if nz > 1 else np.zeros(shape)
+    w.n = np.exp(0.2 * field_())
+    return w
+
+
+def workload(k: int, **kw) -> Workload:
+    """Workload k (1, 2, 3 or 5) at its full size unless overridden."""
+    if k == 1:
+        return shock_tube_1d(**kw)
+    if k == 2:
+        return colliding_slabs_1d(**kw)
+    if k == 3:
+        return shock_cloud_2d(**kw)
+    if k == 5:
+        return blast_wave_3d(**kw)
+    raise ValueError(f"no grid workload {k}")
