@@ -1,0 +1,179 @@
+/*
+ * rlb.h -- C ABI of the MI355X (gfx950) implementation of the per-cell,
+ * per-timestep update of the ultra-relativistic lattice Boltzmann model of
+ * Mohseni, Mendoza, Succi and Herrmann, "Lattice Boltzmann model for
+ * ultra-relativistic flows" (arXiv:1302.1125).
+ *
+ * One update (rlb_step) performs, for every cell, the steps of the extended
+ * model of Sec. II.A:
+ *   1. moments T^{00}, T^{0a} of f and N^0 of h (Eq. (36) and the number
+ *      current of Sec. II);
+ *   2. recovery of eps, u, n with the equation of state eps = 3p (Eq. (38));
+ *   3. the discrete Maxwell-Juttner equilibrium on the extended D3Q19 set
+ *      (Eqs. (29), (36), (42)-(46), moment-exact reading) and the density
+ *      equilibrium (Eq. (58));
+ *   4. minmod flux-limited streaming (Eqs. (47)-(53)) and the bulk-viscosity
+ *      term (Eqs. (54)-(55));
+ *   5. the implicit BGK/Marle update (Eq. (57)), or in Euler mode
+ *      f := f^eq of the post-streaming moments (Sec. III, inviscid case).
+ *
+ * Conventions
+ *   - Every call returns an rlb_status; no C++ exception crosses the ABI.
+ *   - Host field arrays are FP64, length nx*ny*nz, C order [z][y][x]
+ *     (x fastest).  The caller owns them; calls copy synchronously on the
+ *     context's stream.
+ *   - The context owns all device memory (allocated in rlb_create, released
+ *     in rlb_destroy).  Device memory per cell: 2 x 19 populations of f and
+ *     (with density) of h in the storage precision (ping-pong), plus 5 FP64
+ *     fields of the previous step and, with obstacles, 1 byte.
+ *   - Threading: one context per host thread at a time.  Contexts are
+ *     independent.  Results are deterministic for a given configuration
+ *     and device.
+ *   - No CPU fallback exists: without a usable gfx950 device rlb_create
+ *     returns RLB_E_DEVICE.
+ */
+#ifndef RLB_H
+#define RLB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rlb_ctx rlb_ctx; /* opaque */
+
+typedef enum {
+  RLB_OK = 0,
+  RLB_E_INVALID_ARG = -1,   /* bad pointer, size, enum or parameter      */
+  RLB_E_OUT_OF_MEMORY = -2, /* device allocation failed                   */
+  RLB_E_DEVICE = -3,        /* HIP runtime error / no usable device       */
+  RLB_E_INADMISSIBLE = -4,  /* initial fields or a step left the
+                               admissible set (see rlb_step)              */
+  RLB_E_STATE = -5          /* call out of order, or context poisoned by a
+                               previous inadmissible step                */
+} rlb_status;
+
+enum { RLB_FP64 = 0, RLB_MIXED = 1 };              /* storage/arith precision */
+enum { RLB_COLL_IMPLICIT = 0, RLB_COLL_EULER = 1 }; /* Eq. (57) | Sec. III     */
+enum { RLB_TAU_UNIFORM = 0, RLB_TAU_ETA_OVER_S = 1 };
+enum { RLB_BC_PERIODIC = 0, RLB_BC_FIXED = 1, RLB_BC_OUTFLOW = 2 };
+
+/* Run configuration.  Lattice units: delta x = 1. */
+typedef struct {
+  uint32_t struct_size; /* = sizeof(rlb_config) (ABI check)                 */
+  int32_t nx, ny, nz;   /* grid; ny == 1 requires nz == 1; nx >= 2.  Axes
+                           of size 1 must be periodic (quasi-1D / 2D).      */
+  int32_t precision;    /* RLB_FP64: populations stored and updated in FP64.
+                           RLB_MIXED: populations stored and streamed in
+                           FP32; moments accumulated in FP64; recovery and
+                           equilibrium coefficients in FP64.                */
+  int32_t collision;    /* RLB_COLL_IMPLICIT | RLB_COLL_EULER               */
+  int32_t tau_mode;     /* RLB_TAU_UNIFORM: tau given.
+                           RLB_TAU_ETA_OVER_S: per cell from Eq. (41),
+                           tau = 1/2 + nu^2 (eta/s) s/(eps+p), with
+                           s = n (4 - ln(n/T^3)), T = p/n (lattice units,
+                           d_G/pi^2 = 1); without density n = T^3.        */
+  int32_t with_density; /* 1: carry the density distribution h (Eq. (58)) */
+  double nu;            /* nu = c/c_s (Sec. II); > 0                        */
+  double dt_over_dx;    /* time step; (0, 0.5]                              */
+  double tau;           /* relaxation time (RLB_TAU_UNIFORM); > 0           */
+  double eta_over_s;    /* shear viscosity to entropy ratio; >= 0           */
+  double alpha;         /* bulk constant alpha of Eq. (55); >= 0; 0 = off   */
+  int32_t bc[6];        /* faces -x,+x,-y,+y,-z,+z: RLB_BC_*.  Periodic
+                           faces come in pairs.  FIXED ghosts hold the
+                           equilibrium of face_states (the paper's inlet,
+                           Sec. III); OUTFLOW is a zero-gradient copy.      */
+  double face_states[6][5]; /* (eps, ux, uy, uz, n) per FIXED face          */
+  double guard_umax;    /* continuous admissibility guard: 0 = off, else a
+                           speed in (0,1).  After each update a cell whose
+                           new moments leave |T^{0a}| <= m_1 T^{00} is
+                           blended towards the equilibrium of its moments
+                           projected into T^{00} >= floor,
+                           |T^{0a}| <= m_max T^{00} (and n >= floor);
+                           m(u) = 4u/(3+u^2), m_max = m(guard_umax),
+                           m_1 = m(1 - 2(1 - guard_umax)).  Not in the
+                           paper; it is silent on inadmissible states.      */
+  double guard_efloor;  /* floor of T^{00} and n used by the guard; > 0     */
+} rlb_config;
+
+typedef struct {
+  int64_t steps;          /* steps taken since the last rlb_init_fields     */
+  int64_t guard_events;   /* cell-steps in which the guard blended          */
+  int64_t first_bad_step; /* index of the first inadmissible step, or -1   */
+  double sum_T00;         /* domain sums of T^{00}, T^{0a}, N^0 of the     */
+  double sum_T0x;         /* current populations (FP64, fixed reduction    */
+  double sum_T0y;         /* order, so deterministic)                       */
+  double sum_T0z;
+  double sum_N0;
+} rlb_stats;
+
+/* Fill *cfg with defaults: 64x1x1, FP64, implicit, uniform tau = 1,
+   nu = 27^(1/4), dt = 0.25, alpha = 0, no density, periodic, guard off,
+   guard_efloor = 1e-10. */
+rlb_status rlb_config_default(rlb_config* cfg);
+
+/* Validate cfg, allocate device memory on the current HIP device and
+   compute the fixed-face equilibria.  hip_stream: a hipStream_t to run on
+   (e.g. torch's current stream), or NULL for a stream the context creates
+   and owns.  On error *out is NULL and nothing is allocated. */
+rlb_status rlb_create(const rlb_config* cfg, void* hip_stream, rlb_ctx** out);
+
+/* Set the initial fields (Sec. III initial conditions): f := f^eq(eps,u),
+   h := h^eq(n,u) in every cell, and the previous-step fields := these
+   fields (so f^eq(t - dt) = f^eq(t) at the first step).  eps, ux, uy, uz:
+   required; n: required iff with_density (ignored otherwise; the lattice
+   equilibrium density (eps/3)^(3/4) is used); obstacle: NULL or an nx*ny*nz
+   byte mask whose non-zero cells are held at the equilibrium of their
+   initial fields at every step (Sec. III, shock-cloud setup).
+   Returns RLB_E_INADMISSIBLE (state unchanged) if any value is non-finite,
+   eps <= 0, |u| >= 1 or (with density) n <= 0.  Resets the step counter,
+   the guard counter and a poisoned state. */
+rlb_status rlb_init_fields(rlb_ctx* ctx, const double* eps, const double* ux,
+                           const double* uy, const double* uz, const double* n,
+                           const uint8_t* obstacle);
+
+/* Advance nsteps >= 0 updates (one fused kernel launch per update on the
+   context's stream), then synchronise once.  If a step's recovery met a
+   non-obstacle cell with T^{00} <= 0, |T^{0a}| >= T^{00}, N^0 <= 0 (with
+   density) or a non-finite value, returns RLB_E_INADMISSIBLE; rlb_stats
+   reports the first such step and later calls return RLB_E_STATE until
+   rlb_init_fields. */
+rlb_status rlb_step(rlb_ctx* ctx, int64_t nsteps);
+
+/* Enqueue nsteps updates without synchronising or checking (for callers
+   that time or overlap work on the stream).  Check the outcome later with
+   rlb_sync. */
+rlb_status rlb_step_async(rlb_ctx* ctx, int64_t nsteps);
+
+/* Synchronise the context's stream and report inadmissible steps as
+   rlb_step does. */
+rlb_status rlb_sync(rlb_ctx* ctx);
+
+/* Fields of the current populations: eps, u (and n) recovered in FP64 as
+   in step 2.  Any output pointer may be NULL (skipped).  n without density
+   is (eps/3)^(3/4).  Cells whose moments are inadmissible get NaN. */
+rlb_status rlb_moments(rlb_ctx* ctx, double* eps, double* ux, double* uy,
+                       double* uz, double* n);
+
+/* Counters and FP64 domain sums (conservation diagnostics). */
+rlb_status rlb_stats_get(rlb_ctx* ctx, rlb_stats* out);
+
+/* Release the context and its device memory.  NULL is a no-op. */
+void rlb_destroy(rlb_ctx* ctx);
+
+/* Static description of a status code. */
+const char* rlb_status_str(rlb_status s);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* rlb_last_error(void);
+
+/* Device bytes a context with this configuration allocates (0 if cfg is
+   invalid).  Used for memory-based admission. */
+uint64_t rlb_footprint_bytes(const rlb_config* cfg);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RLB_H */

@@ -1,0 +1,234 @@
+"""Python binding of librlb.so (include/rlb.h): argument marshalling only.
+
+Every step of the update runs in the HIP kernels of the library.  There is no
+CPU fallback: importing works anywhere, but creating a context needs the
+built library and a gfx950 device, and fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librlb.so")
+
+RLB_OK = 0
+RLB_E_INVALID_ARG = -1
+RLB_E_OUT_OF_MEMORY = -2
+RLB_E_DEVICE = -3
+RLB_E_INADMISSIBLE = -4
+RLB_E_STATE = -5
+
+RLB_FP64, RLB_MIXED = 0, 1
+RLB_COLL_IMPLICIT, RLB_COLL_EULER = 0, 1
+RLB_TAU_UNIFORM, RLB_TAU_ETA_OVER_S = 0, 1
+RLB_BC_PERIODIC, RLB_BC_FIXED, RLB_BC_OUTFLOW = 0, 1, 2
+
+EXPORTED = [
+    "rlb_config_default", "rlb_create", "rlb_init_fields", "rlb_step", "rlb_step_async",
+    "rlb_sync", "rlb_moments", "rlb_stats_get", "rlb_destroy", "rlb_status_str",
+    "rlb_last_error", "rlb_footprint_bytes",
+]
+
+
+class rlb_config(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("collision", ctypes.c_int32),
+        ("tau_mode", ctypes.c_int32), ("with_density", ctypes.c_int32),
+        ("nu", ctypes.c_double), ("dt_over_dx", ctypes.c_double), ("tau", ctypes.c_double),
+        ("eta_over_s", ctypes.c_double), ("alpha", ctypes.c_double),
+        ("bc", ctypes.c_int32 * 6), ("face_states", (ctypes.c_double * 5) * 6),
+        ("guard_umax", ctypes.c_double), ("guard_efloor", ctypes.c_double),
+    ]
+
+
+class rlb_stats(ctypes.Structure):
+    _fields_ = [
+        ("steps", ctypes.c_int64), ("guard_events", ctypes.c_int64),
+        ("first_bad_step", ctypes.c_int64),
+        ("sum_T00", ctypes.c_double), ("sum_T0x", ctypes.c_double),
+        ("sum_T0y", ctypes.c_double), ("sum_T0z", ctypes.c_double), ("sum_N0", ctypes.c_double),
+    ]
+
+
+class RLBError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load librlb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RLBError(RLB_E_DEVICE, f"HIP library not built: {path} (run __graft_entry__.build())")
+    try:
+        # Load torch's HIP runtime first (same soname), so that the process
+        # holds a single runtime and torch streams can be handed to the library.
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    vp = ctypes.c_void_p
+    L.rlb_config_default.argtypes = [ctypes.POINTER(rlb_config)]
+    L.rlb_create.argtypes = [ctypes.POINTER(rlb_config), vp, ctypes.POINTER(vp)]
+    L.rlb_init_fields.argtypes = [vp, dp, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_uint8)]
+    L.rlb_step.argtypes = [vp, ctypes.c_int64]
+    L.rlb_step_async.argtypes = [vp, ctypes.c_int64]
+    L.rlb_sync.argtypes = [vp]
+    L.rlb_moments.argtypes = [vp, dp, dp, dp, dp, dp]
+    L.rlb_stats_get.argtypes = [vp, ctypes.POINTER(rlb_stats)]
+    L.rlb_destroy.argtypes = [vp]
+    L.rlb_destroy.restype = None
+    L.rlb_status_str.argtypes = [ctypes.c_int]
+    L.rlb_status_str.restype = ctypes.c_char_p
+    L.rlb_last_error.argtypes = []
+    L.rlb_last_error.restype = ctypes.c_char_p
+    L.rlb_footprint_bytes.argtypes = [ctypes.POINTER(rlb_config)]
+    L.rlb_footprint_bytes.restype = ctypes.c_uint64
+    for name in ("rlb_config_default", "rlb_create", "rlb_init_fields", "rlb_step",
+                 "rlb_step_async", "rlb_sync", "rlb_moments", "rlb_stats_get"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != RLB_OK:
+        L = load()
+        raise RLBError(status, f"{L.rlb_status_str(status).decode()}: {L.rlb_last_error().decode()}")
+
+
+def _dp(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64)).reshape(-1)
+
+
+def rlb_config_default() -> rlb_config:
+    c = rlb_config()
+    _check(load().rlb_config_default(ctypes.byref(c)))
+    return c
+
+
+def config_from(nx, ny=1, nz=1, precision=RLB_FP64, collision=RLB_COLL_IMPLICIT,
+                tau_mode=RLB_TAU_UNIFORM, with_density=False, nu=27.0 ** 0.25, dt_over_dx=0.25,
+                tau=1.0, eta_over_s=0.0, alpha=0.0, bc: Sequence[int] = (0,) * 6,
+                face_states=None, guard_umax=0.0, guard_efloor=1e-10) -> rlb_config:
+    c = rlb_config_default()
+    c.nx, c.ny, c.nz = int(nx), int(ny), int(nz)
+    c.precision, c.collision, c.tau_mode = int(precision), int(collision), int(tau_mode)
+    c.with_density = int(bool(with_density))
+    c.nu, c.dt_over_dx, c.tau = float(nu), float(dt_over_dx), float(tau)
+    c.eta_over_s, c.alpha = float(eta_over_s), float(alpha)
+    for k in range(6):
+        c.bc[k] = int(bc[k])
+        if face_states is not None:
+            for j in range(5):
+                c.face_states[k][j] = float(face_states[k][j])
+    c.guard_umax, c.guard_efloor = float(guard_umax), float(guard_efloor)
+    return c
+
+
+def config_for_workload(w, precision=None) -> rlb_config:
+    """rlb_config of a paper_1302_1125_amd.workloads.Workload."""
+    return config_from(w.nx, w.ny, w.nz, precision=w.precision if precision is None else precision,
+                       collision=w.collision, tau_mode=w.tau_mode, with_density=w.with_density,
+                       nu=w.nu, dt_over_dx=w.dt, tau=w.tau, eta_over_s=w.eta_over_s, alpha=w.alpha,
+                       bc=w.bc, face_states=w.face_states, guard_umax=w.guard_umax,
+                       guard_efloor=w.guard_efloor)
+
+
+def rlb_footprint_bytes(cfg: rlb_config) -> int:
+    return int(load().rlb_footprint_bytes(ctypes.byref(cfg)))
+
+
+class Context:
+    """Owner of one rlb_ctx.  Methods map 1:1 onto the C calls."""
+
+    def __init__(self, cfg: rlb_config, stream: Optional[int] = None):
+        self._L = load()
+        self.cfg = cfg
+        h = ctypes.c_void_p()
+        _check(self._L.rlb_create(ctypes.byref(cfg), ctypes.c_void_p(stream) if stream else None,
+                                  ctypes.byref(h)))
+        self._h = h
+        self.shape = (cfg.nz, cfg.ny, cfg.nx)
+        self.ncell = cfg.nx * cfg.ny * cfg.nz
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.rlb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def rlb_init_fields(self, eps, ux, uy, uz, n=None, obstacle=None):
+        a = [_f64(v) for v in (eps, ux, uy, uz)]
+        for v in a:
+            if v.size != self.ncell:
+                raise ValueError("field size does not match the grid")
+        nn = None if n is None else _f64(n)
+        ob = None
+        if obstacle is not None:
+            ob = np.ascontiguousarray(np.asarray(obstacle, dtype=np.uint8)).reshape(-1)
+            if ob.size != self.ncell:
+                raise ValueError("obstacle size does not match the grid")
+        _check(self._L.rlb_init_fields(
+            self._h, _dp(a[0]), _dp(a[1]), _dp(a[2]), _dp(a[3]), _dp(nn),
+            None if ob is None else ob.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+
+    def rlb_step(self, nsteps: int):
+        _check(self._L.rlb_step(self._h, int(nsteps)))
+
+    def rlb_step_async(self, nsteps: int):
+        _check(self._L.rlb_step_async(self._h, int(nsteps)))
+
+    def rlb_sync(self):
+        _check(self._L.rlb_sync(self._h))
+
+    def rlb_moments(self):
+        """(eps, ux, uy, uz, n) as float64 arrays of shape [nz, ny, nx]."""
+        out = [np.empty(self.ncell) for _ in range(5)]
+        _check(self._L.rlb_moments(self._h, *[_dp(o) for o in out]))
+        return [o.reshape(self.shape) for o in out]
+
+    def rlb_stats_get(self) -> rlb_stats:
+        s = rlb_stats()
+        _check(self._L.rlb_stats_get(self._h, ctypes.byref(s)))
+        return s
+
+    def status_of_step(self, nsteps: int) -> int:
+        """rlb_step returning the raw status instead of raising."""
+        return int(self._L.rlb_step(self._h, int(nsteps)))
+
+
+def context_for_workload(w, precision=None, stream=None, init=True) -> Context:
+    ctx = Context(config_for_workload(w, precision), stream)
+    if init:
+        ctx.rlb_init_fields(w.eps, w.ux, w.uy, w.uz, w.n if w.with_density else None, w.obstacle)
+    return ctx

@@ -1,0 +1,57 @@
+"""The C-ABI library loads and exports every function include/rlb.h declares
+(no GPU needed: nothing here launches a kernel)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rlb.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rlb_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("rlb_create", "rlb_init_fields", "rlb_step", "rlb_moments", "rlb_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1302_1125_amd import rlb
+    if not os.path.exists(rlb.LIB_PATH):
+        pytest.skip("librlb.so not built")
+    lib = ctypes.CDLL(rlb.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert sorted(rlb.EXPORTED) == declared_functions()
+
+
+def test_struct_layout_matches_header():
+    from paper_1302_1125_amd import rlb
+    # sizeof(rlb_config) in C: 4 + 3*4 + 4*4 + 5*8 + 6*4 + 30*8 + 2*8, padded to 8
+    assert ctypes.sizeof(rlb.rlb_config) == 352
+    assert ctypes.sizeof(rlb.rlb_stats) == 64
+
+
+def test_host_side_validation_without_device():
+    """Status strings and config defaults need no GPU; footprints follow the
+    stated per-cell layout."""
+    from paper_1302_1125_amd import rlb
+    if not os.path.exists(rlb.LIB_PATH):
+        pytest.skip("librlb.so not built")
+    L = rlb.load()
+    assert L.rlb_status_str(0).decode() == "ok"
+    c = rlb.config_from(1000, with_density=False)
+    assert rlb.rlb_footprint_bytes(c) >= 1000 * (2 * 19 * 8 + 5 * 8)
+    m = rlb.config_from(128, 64, 32, precision=rlb.RLB_MIXED, with_density=True)
+    n = 128 * 64 * 32
+    fp = rlb.rlb_footprint_bytes(m)
+    assert n * (4 * 19 * 4 + 5 * 8) <= fp <= n * (4 * 19 * 4 + 5 * 8) * 1.01 + 4096
+    bad = rlb.config_from(8, 1, 4)
+    assert rlb.rlb_footprint_bytes(bad) == 0
