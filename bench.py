@@ -135,7 +135,9 @@ def main():
     torch.cuda.set_device(0)
     precision = rlb.RLB_MIXED if args.precision == "mixed" else rlb.RLB_FP64
     w = make_workload(args.workload, precision)
-    stream = torch.cuda.current_stream()
+    # a dedicated stream (default priority): the library launches on it and
+    # the timing events are recorded on it
+    stream = torch.cuda.Stream()
     print(f"[bench] workload {w.name} {w.nx}x{w.ny}x{w.nz} {args.precision} h={w.with_density} "
           f"steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
     ctx = rlb.context_for_workload(w, precision=precision, stream=stream.cuda_stream)

@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -45,7 +46,6 @@ struct rlb_ctx {
   int cur = 0;
   double* hist = nullptr;
   uint8_t* obst = nullptr;
-  double* face_eq = nullptr;       // [6][2][19]
   double* face_states = nullptr;   // [6][5]
   unsigned long long* counters = nullptr;  // [0] bad step, [1] guard events, [2] moments flag
   unsigned long long* host_counters = nullptr;  // pinned copy
@@ -69,7 +69,7 @@ rlb_status validate(const rlb_config* c) {
   if (c->nx < 2 || c->ny < 1 || c->nz < 1) return fail(RLB_E_INVALID_ARG, "grid: nx >= 2, ny, nz >= 1");
   if (c->ny == 1 && c->nz != 1) return fail(RLB_E_INVALID_ARG, "ny == 1 requires nz == 1");
   const long long nc = static_cast<long long>(c->nx) * c->ny * c->nz;
-  if (nc > (1ll << 40)) return fail(RLB_E_INVALID_ARG, "grid too large");
+  if (nc > (1ll << 31) - 64) return fail(RLB_E_INVALID_ARG, "grid too large (at most 2^31 - 64 cells)");
   if (c->precision != RLB_FP64 && c->precision != RLB_MIXED) return fail(RLB_E_INVALID_ARG, "precision");
   if (c->collision != RLB_COLL_IMPLICIT && c->collision != RLB_COLL_EULER)
     return fail(RLB_E_INVALID_ARG, "collision");
@@ -104,12 +104,13 @@ rlb_status validate(const rlb_config* c) {
 
 uint64_t footprint(const rlb_config* c) {
   const uint64_t nc = static_cast<uint64_t>(c->nx) * c->ny * c->nz;
+  const uint64_t ps = static_cast<uint64_t>(rlb::population_stride(static_cast<long long>(nc)));
   const uint64_t elem = c->precision == RLB_FP64 ? 8 : 4;
-  uint64_t b = 2 * rlb::Q * nc * elem;            // f, ping-pong
-  if (c->with_density) b += 2 * rlb::Q * nc * elem;
+  uint64_t b = 2 * rlb::Q * ps * elem;            // f, ping-pong
+  if (c->with_density) b += 2 * rlb::Q * ps * elem;
   b += 5 * nc * 8;                                // previous-step fields
   b += (nc + 255) / 256 * 5 * 8;                  // reduction partials
-  b += 6 * 2 * rlb::Q * 8 + 6 * 5 * 8 + 64 + 64;
+  b += 6 * 5 * 8 + 4 * 8 + 8 * 8;                 // face states, counters, sums
   return b;
 }
 
@@ -120,7 +121,6 @@ void free_all(rlb_ctx* x) {
   }
   if (x->hist) (void)hipFree(x->hist);
   if (x->obst) (void)hipFree(x->obst);
-  if (x->face_eq) (void)hipFree(x->face_eq);
   if (x->face_states) (void)hipFree(x->face_states);
   if (x->counters) (void)hipFree(x->counters);
   if (x->host_counters) (void)hipHostFree(x->host_counters);
@@ -141,11 +141,18 @@ rlb_status dalloc(P** p, size_t bytes, const char* what) {
   return RLB_OK;
 }
 
+int largest_divisor_at_most(int n, int cap) {
+  for (int d = cap < n ? cap : n; d > 1; --d)
+    if (n % d == 0) return d;
+  return 1;
+}
+
 void fill_params(rlb_ctx* x) {
   const rlb_config& c = x->cfg;
   rlb::StepParams& p = x->base;
   p = rlb::StepParams{};
   p.ncell = x->ncell;
+  p.pstride = rlb::population_stride(x->ncell);
   p.nx = c.nx;
   p.ny = c.ny;
   p.nz = c.nz;
@@ -159,7 +166,29 @@ void fill_params(rlb_ctx* x) {
   p.ntx = (c.nx + p.tile_x - 1) / p.tile_x;
   p.nty = (c.ny + p.tile_y - 1) / p.tile_y;
   p.ntiles = static_cast<long long>(p.ntx) * p.nty * c.nz;
-  p.tiles_per_xcd = (p.ntiles + rlb::kXcds - 1) / rlb::kXcds;
+  // Pencil shape: the largest divisors of ntx / nty not above the targets
+  // (3D: 8 x 4 tiles = 512 x 16 cells marched in z; 2D: strips 16 tiles
+  // wide), chosen by measurement on MI355X.
+  int want_w = c.nz > 1 ? 8 : 16, want_h = c.nz > 1 ? 4 : 1 << 30;
+  if (const char* e = std::getenv("RLB_PENCIL")) {  // tuning override "pw,ph"
+    int a = 0, b = 0;
+    if (std::sscanf(e, "%d,%d", &a, &b) == 2 && a > 0 && b > 0) {
+      want_w = a;
+      want_h = b;
+    }
+  }
+  p.pw = largest_divisor_at_most(p.ntx, want_w);
+  p.ph = largest_divisor_at_most(p.nty, want_h);
+  if (c.nz >= rlb::kXcds) {
+    // 3D: each XCD owns a z-slab and marches pencils through it
+    p.order = 1;
+    p.zslab = (c.nz + rlb::kXcds - 1) / rlb::kXcds;
+    p.tiles_per_xcd = static_cast<long long>(p.zslab) * p.ntx * p.nty;
+  } else {
+    p.order = 0;
+    p.zslab = 1;
+    p.tiles_per_xcd = (p.ntiles + rlb::kXcds - 1) / rlb::kXcds;
+  }
   for (int k = 0; k < 6; ++k) p.bc[k] = c.bc[k];
   const double nu = c.nu;
   p.a_scale = nu * nu / 27.0;
@@ -184,10 +213,10 @@ void fill_params(rlb_ctx* x) {
     p.mmax = 4.0 * um / (3.0 + um * um);
     p.m1 = 4.0 * u1 / (3.0 + u1 * u1);
     p.efloor = c.guard_efloor;
+    p.gmax = 1.0 / std::sqrt((1.0 - um) * (1.0 + um));
   }
   p.hist = x->hist;
   p.obst = nullptr;
-  p.face_eq = x->face_eq;
   p.bad_step = x->counters;
   p.guard_count = x->counters + 1;
 }
@@ -292,7 +321,7 @@ rlb_status rlb_create(const rlb_config* cfg, void* hip_stream, rlb_ctx** out) {
     }
     x->own_stream = true;
   }
-  const size_t pop_bytes = static_cast<size_t>(rlb::Q) * x->ncell * x->elem;
+  const size_t pop_bytes = static_cast<size_t>(rlb::Q) * rlb::population_stride(x->ncell) * x->elem;
   x->sums_blocks = static_cast<int>((x->ncell + rlb::kBlock - 1) / rlb::kBlock);
   st = RLB_OK;
   for (int k = 0; k < 2 && st == RLB_OK; ++k) {
@@ -300,7 +329,6 @@ rlb_status rlb_create(const rlb_config* cfg, void* hip_stream, rlb_ctx** out) {
     if (st == RLB_OK && cfg->with_density) st = dalloc(&x->h[k], pop_bytes, "h");
   }
   if (st == RLB_OK) st = dalloc(&x->hist, 5 * sizeof(double) * x->ncell, "fields");
-  if (st == RLB_OK) st = dalloc(&x->face_eq, 6 * 2 * rlb::Q * sizeof(double), "face_eq");
   if (st == RLB_OK) st = dalloc(&x->face_states, 6 * 5 * sizeof(double), "face_states");
   if (st == RLB_OK) st = dalloc(&x->counters, 4 * sizeof(unsigned long long), "counters");
   if (st == RLB_OK) st = dalloc(&x->sums_partial, static_cast<size_t>(x->sums_blocks) * 5 * sizeof(double), "sums");
@@ -317,7 +345,9 @@ rlb_status rlb_create(const rlb_config* cfg, void* hip_stream, rlb_ctx** out) {
   fill_params(x);
   e = hipMemcpyAsync(x->face_states, cfg->face_states, 6 * 5 * sizeof(double), hipMemcpyHostToDevice,
                      x->stream);
-  if (e == hipSuccess) e = rlb::launch_face_eq(x->base, x->face_states, x->face_eq, x->stream);
+  if (e == hipSuccess)
+    e = rlb::launch_face_slots(x->base, x->fp64, x->face_states, x->f[0], x->f[1], x->h[0], x->h[1],
+                               x->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
   if (e != hipSuccess) {
     st = hip_fail(e, "face equilibria");

@@ -11,7 +11,18 @@ namespace rlb {
 constexpr int Q = 19;            // extended D3Q19 set, Sec. II.A, Eq. (42)
 constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts)
 constexpr int kXcds = 8;         // MI355X: 8 XCDs, workgroups dispatched round-robin
+constexpr int kFaceSlots = 6;    // per population: equilibria of the 6 faces
 constexpr int kBcPeriodic = 0, kBcFixed = 1, kBcOutflow = 2;
+
+// Population arrays hold pstride elements per population: cells
+// [0, ncell) in the order x + nx (y + ny z), then one slot per face
+// [ncell, ncell + 6) holding the equilibrium of that face's fixed state
+// (written once at creation in both ping-pong copies).  A neighbour index
+// that crosses a FIXED face points at the face slot, so boundary conditions
+// are pure index mapping inside the step kernel.
+inline long long population_stride(long long ncell) {
+  return (ncell + kFaceSlots + 63) / 64 * 64;
+}
 
 // Everything a step kernel needs, passed by value (kernarg segment).
 struct StepParams {
@@ -21,13 +32,23 @@ struct StepParams {
   void* h_out;
   double* hist;            // [5][ncell]: eps, ux, uy, uz, n of the previous step
   const uint8_t* obst;     // [ncell] or nullptr
-  const double* face_eq;   // [6 faces][2: f,h][19] equilibria of FIXED faces
   long long ncell;
+  long long pstride;       // elements per population array (population_stride)
   int nx, ny, nz;
-  int tile_x, tile_y;      // workgroup tile (tile_x * tile_y == kBlock)
-  int ntx, nty;            // tiles along x and y
-  long long ntiles;        // ntx * nty * nz
-  long long tiles_per_xcd; // ceil(ntiles / kXcds)
+  // Workgroup tiling: tile_x * tile_y == kBlock cells of one z-plane, and a
+  // traversal order that keeps stencil reuse inside one XCD's L2.  Tiles are
+  // grouped into pencils of pw x ph tiles (pw divides ntx, ph divides nty).
+  // order 0 (1D/2D): linear index runs x-tiles of a pencil fastest, then
+  //   y-tiles, then z, then pencils; XCD k takes the k-th contiguous chunk.
+  // order 1 (3D): XCD k takes z-slab [k zslab, (k+1) zslab); inside it the
+  //   index runs the tiles of one pencil plane fastest, then z, then pencils.
+  int order;
+  int tile_x, tile_y;
+  int ntx, nty;
+  int pw, ph;
+  int zslab;
+  long long ntiles;        // tiles in the grid
+  long long tiles_per_xcd; // tiles assigned to each XCD (grid = 8 * this)
   int bc[6];
   // lattice and run constants (FP64)
   double a_scale;   // nu^2 / 27: equilibrium amplitude A = a_scale * eps
@@ -45,6 +66,7 @@ struct StepParams {
   int tau_mode;     // 0 uniform, 1 eta/s
   int guard;        // 0/1
   double m1, mmax, efloor;
+  double gmax;      // Lorentz factor at m_max (bounds gamma of projected moments)
   unsigned long long* bad_step;    // atomicMin of the first inadmissible step
   unsigned long long* guard_count; // cell-steps blended by the guard
   long long step_index;
@@ -54,8 +76,8 @@ struct StepParams {
 hipError_t launch_step(const StepParams& p, bool fp64, int act_mask, bool with_h, bool euler,
                        hipStream_t s);
 hipError_t launch_init(const StepParams& p, bool fp64, bool with_h, hipStream_t s);
-hipError_t launch_face_eq(const StepParams& p, const double* face_states_dev, double* face_eq_dev,
-                          hipStream_t s);
+hipError_t launch_face_slots(const StepParams& p, bool fp64, const double* face_states_dev,
+                             void* f0, void* f1, void* h0, void* h1, hipStream_t s);
 hipError_t launch_moments(const StepParams& p, bool fp64, bool with_h, double* out /*[5][ncell]*/,
                           unsigned long long* bad_flag, hipStream_t s);
 hipError_t launch_sums(const StepParams& p, bool fp64, bool with_h, double* partial, int nblocks,

@@ -1,17 +1,22 @@
 // rlb_kernels.hip -- gfx950 kernels of the ultra-relativistic lattice
 // Boltzmann update of Mohseni, Mendoza, Succi and Herrmann (arXiv:1302.1125).
 //
-// Data layout (HBM): populations structure-of-arrays, f[i][cell] and
-// h[i][cell], cell = x + nx (y + ny z), two copies (ping-pong); the fields of
-// the previous step hist[k][cell] (FP64, k = eps, ux, uy, uz, n) are read and
-// rewritten in place by the cell that owns them.
+// Data layout (HBM): populations structure-of-arrays f[i][cell] and
+// h[i][cell] with cell = x + nx (y + ny z) and a per-population stride that
+// leaves six face slots after the cells (rlb_internal.h); two copies
+// (ping-pong).  The fields of the previous step hist[k][cell] (FP64,
+// k = eps, ux, uy, uz, n) are read and rewritten in place by their cell.
 //
-// One fused kernel per step: each thread owns one cell, forms its moments
-// (FP64 accumulation), recovers the fields in FP64, builds the equilibrium
-// coefficients in FP64, and for every population evaluates the minmod
-// limited flux divergence, the bulk Laplacian and the implicit collision in
-// the storage precision.  Workgroups cover 2D tiles of cells; the tile index
-// is remapped so that each XCD (own L2) walks a contiguous range of tiles.
+// One fused kernel per step, one thread per cell.  The thread forms its
+// moments (FP64 accumulation), recovers the fields in FP64 and builds the
+// equilibrium coefficients in FP64; then, one population at a time, it
+// loads the star stencil (absolute neighbour indices precomputed once per
+// cell, boundary conditions folded into them), evaluates the minmod-limited
+// flux divergence, the bulk Laplacian and the implicit collision in the
+// storage precision and stores the result at once, so only the centre
+// values and the coefficient sets stay live.  The admissibility guard is
+// gated by a cheap storage-precision test of the new moments with a
+// rounding margin, and re-decided in FP64 from the stored values.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -74,30 +79,36 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
-// XCD-aware tile index: workgroup b runs on XCD b % 8; give XCD x the
-// contiguous tile range [x * per, (x + 1) * per).
-__device__ __forceinline__ long long xcd_tile(unsigned b, long long per) {
-  return static_cast<long long>(b % kXcds) * per + static_cast<long long>(b / kXcds);
+template <int ACT>
+__host__ __device__ constexpr bool axis_on(int a) {
+  return (ACT >> a) & 1;
 }
 
-// Equilibrium as a linear form in 10 coefficients:
+template <int ACT>
+__host__ __device__ constexpr int n_axes() {
+  return (ACT & 1) + ((ACT >> 1) & 1) + ((ACT >> 2) & 1);
+}
+
+// ---------------------------------------------------------------------------
+// Equilibria as linear forms in 10 coefficients:
 // bracket_i(K) = K0 + sum_a e^a K[1+a] + sum_a (e^a)^2 K[4+a]
 //              + e^x e^y K7 + e^x e^z K8 + e^y e^z K9.
-template <int I>
-__device__ __forceinline__ double bracket(const double* K) {
+// ---------------------------------------------------------------------------
+template <int I, typename C>
+__device__ __forceinline__ C bracket(const C* K) {
   constexpr Vel e = vel(I);
-  double s = K[0];
-  if constexpr (e.x != 0) s += double(e.x) * K[1] + double(e.x * e.x) * K[4];
-  if constexpr (e.y != 0) s += double(e.y) * K[2] + double(e.y * e.y) * K[5];
-  if constexpr (e.z != 0) s += double(e.z) * K[3] + double(e.z * e.z) * K[6];
-  if constexpr (e.x * e.y != 0) s += double(e.x * e.y) * K[7];
-  if constexpr (e.x * e.z != 0) s += double(e.x * e.z) * K[8];
-  if constexpr (e.y * e.z != 0) s += double(e.y * e.z) * K[9];
+  C s = K[0];
+  if constexpr (e.x != 0) s += C(e.x) * K[1] + C(e.x * e.x) * K[4];
+  if constexpr (e.y != 0) s += C(e.y) * K[2] + C(e.y * e.y) * K[5];
+  if constexpr (e.z != 0) s += C(e.z) * K[3] + C(e.z * e.z) * K[6];
+  if constexpr (e.x * e.y != 0) s += C(e.x * e.y) * K[7];
+  if constexpr (e.x * e.z != 0) s += C(e.x * e.z) * K[8];
+  if constexpr (e.y * e.z != 0) s += C(e.y * e.z) * K[9];
   return s;
 }
 
-// f^eq_i = w_i bracket_i(K) with (moment-exact reading of Eq. (29), fixed by
-// Eq. (36) and eps = 3p): A = nu^2 eps / 27, G = A gamma^2,
+// f^eq_i = w_i bracket_i(K) (moment-exact reading of Eq. (29), fixed by
+// Eq. (36) with eps = 3p): A = nu^2 eps / 27, G = A gamma^2,
 // K0 = A - 16/15 G |u|^2, K_a = 4 sqrt(13/27) G u^a, K_aa = 52/15 G (u^a)^2,
 // K_ab = 13 G u^a u^b.
 __device__ __forceinline__ void feq_coeffs(const StepParams& P, double eps, double ux, double uy,
@@ -106,7 +117,7 @@ __device__ __forceinline__ void feq_coeffs(const StepParams& P, double eps, doub
   const double G = A * g2;
   const double u2 = ux * ux + uy * uy + uz * uz;
   K[0] = A - (16.0 / 15.0) * G * u2;
-  const double c1 = P.k1 * G;  // 4 sqrt(13/27) G
+  const double c1 = P.k1 * G;
   K[1] = c1 * ux;
   K[2] = c1 * uy;
   K[3] = c1 * uz;
@@ -141,8 +152,9 @@ __device__ __forceinline__ void heq_coeffs(const StepParams& P, double n, double
   H[9] = 2.0 * c2 * uy * uz;
 }
 
-__device__ __forceinline__ double wprime(const StepParams& P, int i) {
-  return i == 0 ? P.wp0 : (i <= 6 ? P.wp1 : P.wp2);
+template <int I>
+__device__ __forceinline__ double wprime(const StepParams& P) {
+  return I == 0 ? P.wp0 : (I <= 6 ? P.wp1 : P.wp2);
 }
 
 // Fields from T^{00} = E, T^{0a} = M^a, N^0 with eps = 3p:
@@ -177,135 +189,209 @@ __device__ __forceinline__ bool recover(double E, double Mx, double My, double M
 // Local relaxation time: uniform, or Eq. (41) with the entropy density of
 // Sec. III, s = n (4 - ln lambda), lambda = n / T^3, T = p / n (lattice units);
 // without density lambda = 1 and n = T^3 so tau = 1/2 + nu^2 (eta/s) / T.
-template <bool WH>
+// In mixed precision the relaxation time (a rate of the FP32 collision) is
+// evaluated in FP32.
+#ifndef RLB_TAU_F64
+#define RLB_TAU_F64 0
+#endif
+template <typename T, bool WH>
 __device__ __forceinline__ double tau_of(const StepParams& P, const Fields& F) {
   if (P.tau_mode == 0) return P.tau;
-  const double p = F.eps / 3.0;
-  if constexpr (WH) {
-    const double T = p / F.n;
-    const double lam = F.n / (T * T * T);
-    const double s = F.n * (4.0 - log(lam));
-    return 0.5 + P.nu2_etas * s / (F.eps + p);
+  if constexpr (sizeof(T) == 4 && !RLB_TAU_F64) {
+    const float eps = static_cast<float>(F.eps), n = static_cast<float>(F.n);
+    const float p = eps * (1.0f / 3.0f);
+    const float c = static_cast<float>(P.nu2_etas);
+    if constexpr (WH) {
+      // ln lambda = ln n - 3 ln T = 4 ln n - 3 ln p (no overflow of T^3)
+      const float s = n * (4.0f - (4.0f * __logf(n) - 3.0f * __logf(p)));
+      return 0.5 + static_cast<double>(c * s / (eps + p));
+    } else {
+      return 0.5 + static_cast<double>(c * __frsqrt_rn(__fsqrt_rn(p)));
+    }
   } else {
-    return 0.5 + P.nu2_etas / sqrt(sqrt(p));
+    const double p = F.eps / 3.0;
+    if constexpr (WH) {
+      const double T_ = p / F.n;
+      const double lam = F.n / (T_ * T_ * T_);
+      const double s = F.n * (4.0 - log(lam));
+      return 0.5 + P.nu2_etas * s / (F.eps + p);
+    } else {
+      return 0.5 + P.nu2_etas / sqrt(sqrt(p));
+    }
   }
 }
 
-// minmod(X, Y), Eq. (53): the argument of smaller magnitude if both have the
-// same sign, else 0.
-template <typename T>
-__device__ __forceinline__ T mmod(T a, T b) {
-  const T lo = fmin(a, b), hi = fmax(a, b);
-  return (a > T(0) && b > T(0)) ? lo : ((a < T(0) && b < T(0)) ? hi : T(0));
+// minmod(X, Y), Eq. (53): the argument of smaller magnitude when both have
+// the same sign, otherwise 0.  That is exactly the median of (X, Y, 0): one
+// v_med3_f32 in single precision.
+__device__ __forceinline__ float mmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
+__device__ __forceinline__ double mmod(double a, double b) {
+  return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
 }
 
 // Difference of limited interface values between x + 1/2 and x - 1/2 for a
 // positive streaming speed (left states): values at x-2, x-1, x, x+1.
 template <typename T>
 __device__ __forceinline__ T dflux_pos(T m2, T m1, T c0, T p1) {
-  const T g0 = c0 + T(0.5) * mmod(p1 - c0, c0 - m1);
-  const T gm = m1 + T(0.5) * mmod(c0 - m1, m1 - m2);
-  return g0 - gm;
+  const T d0 = c0 - m1;
+  return d0 + T(0.5) * (mmod(p1 - c0, d0) - mmod(d0, m1 - m2));
 }
 
 // Same for a negative speed (right states): values at x-1, x, x+1, x+2.
 template <typename T>
 __device__ __forceinline__ T dflux_neg(T m1, T c0, T p1, T p2) {
-  const T q0 = p1 - T(0.5) * mmod(p2 - p1, p1 - c0);
-  const T qm = c0 - T(0.5) * mmod(p1 - c0, c0 - m1);
-  return q0 - qm;
+  const T d1 = p1 - c0;
+  return d1 - T(0.5) * (mmod(p2 - p1, d1) - mmod(d1, c0 - m1));
 }
 
-// Cell coordinates and neighbour addressing with boundary conditions folded
-// into the index (periodic wrap, outflow clamp) or the value (fixed face).
-template <typename T>
-struct Cell {
-  int x[3];
-  int n[3];
-  long long stride[3];
-  long long c;
-  bool inner;  // every active axis has >= 2 cells on both sides
-
-  __device__ __forceinline__ T load(const T* __restrict__ arr, const StepParams& P, int pop,
-                                    int dist, int a, int k) const {
-    if (inner) return arr[c + k * stride[a]];
-    int q = x[a] + k;
-    if (q < 0) {
-      const int b = P.bc[2 * a];
-      if (b == kBcFixed) return static_cast<T>(P.face_eq[((2 * a) * 2 + dist) * Q + pop]);
-      q = (b == kBcPeriodic) ? q + n[a] : 0;
-    } else if (q >= n[a]) {
-      const int b = P.bc[2 * a + 1];
-      if (b == kBcFixed) return static_cast<T>(P.face_eq[((2 * a + 1) * 2 + dist) * Q + pop]);
-      q = (b == kBcPeriodic) ? q - n[a] : n[a] - 1;
-    }
-    return arr[c + static_cast<long long>(q - x[a]) * stride[a]];
-  }
+// Byte offsets (32-bit) of a cell and of its neighbours within one
+// population array, for offsets -2, -1, +1, +2 along each active axis, with
+// periodic wrap, outflow clamp or the face slot of a FIXED face folded in.
+// Loads then take the form base_i + offset with base_i = array + i * stride
+// uniform across the wavefront (scalar base, 32-bit vector offset).
+template <int ACT>
+struct Nbr {
+  unsigned c;
+  unsigned o[3][4];
 };
 
-template <int ACT>
-__device__ __forceinline__ bool axis_on(int a) {
-  return (ACT >> a) & 1;
+template <typename T, int ACT>
+__device__ __forceinline__ void make_nbr(const StepParams& P, int x, int y, int z, Nbr<ACT>& N) {
+  const int co[3] = {x, y, z};
+  const int n[3] = {P.nx, P.ny, P.nz};
+  const long long st[3] = {1, P.nx, static_cast<long long>(P.nx) * P.ny};
+  const long long c = x + static_cast<long long>(P.nx) * (y + static_cast<long long>(P.ny) * z);
+  N.c = static_cast<unsigned>(c) * static_cast<unsigned>(sizeof(T));
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (!axis_on<ACT>(a)) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = j < 2 ? j - 2 : j - 1;
+      const int q = co[a] + k;
+      long long idx = c + k * st[a];
+      if (q < 0 || q >= n[a]) {
+        const int side = q < 0 ? 0 : 1;
+        const int b = P.bc[2 * a + side];
+        if (b == kBcFixed) idx = P.ncell + 2 * a + side;
+        else if (b == kBcPeriodic) idx = c + (q < 0 ? k + n[a] : k - n[a]) * st[a];
+        else idx = c + ((q < 0 ? 0 : n[a] - 1) - co[a]) * st[a];
+      }
+      N.o[a][j] = static_cast<unsigned>(idx) * static_cast<unsigned>(sizeof(T));
+    }
+  }
 }
 
-// delta t * (flux divergence) and the Laplacian of population I at the cell.
+template <typename T>
+__device__ __forceinline__ T ldb(const T* __restrict__ base, unsigned off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+
+template <typename T>
+__device__ __forceinline__ void stb(T* __restrict__ base, unsigned off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
+}
+
+// Star stencil of one population: per active axis the values the limited
+// flux (and, with LAP, the Laplacian) needs: e^a > 0: x-2, x-1, x+1;
+// e^a < 0: x-1, x+1, x+2; e^a = 0 with LAP: x-1, x+1.
+template <typename T>
+struct Sten {
+  T v[3][3];
+};
+
 template <typename T, int ACT, int I, bool LAP>
-__device__ __forceinline__ void stream_terms(const T* __restrict__ arr_i, const StepParams& P,
-                                             const Cell<T>& C, int dist, T c0, T dtv, T& dD,
-                                             T& lap) {
-  dD = T(0);
-  lap = T(0);
+__device__ __forceinline__ void gather(const T* __restrict__ arr, const Nbr<ACT>& N, Sten<T>& s) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (!axis_on<ACT>(a)) continue;
     const int ea = vcomp(I, a);
     if (ea > 0) {
-      const T m2 = C.load(arr_i, P, I, dist, a, -2);
-      const T m1 = C.load(arr_i, P, I, dist, a, -1);
-      const T p1 = C.load(arr_i, P, I, dist, a, +1);
-      dD += (dtv * T(ea)) * dflux_pos(m2, m1, c0, p1);
-      if (LAP) lap += (m1 + p1) - T(2) * c0;
+      s.v[a][0] = ldb(arr, N.o[a][0]);
+      s.v[a][1] = ldb(arr, N.o[a][1]);
+      s.v[a][2] = ldb(arr, N.o[a][2]);
     } else if (ea < 0) {
-      const T m1 = C.load(arr_i, P, I, dist, a, -1);
-      const T p1 = C.load(arr_i, P, I, dist, a, +1);
-      const T p2 = C.load(arr_i, P, I, dist, a, +2);
-      dD += (dtv * T(ea)) * dflux_neg(m1, c0, p1, p2);
-      if (LAP) lap += (m1 + p1) - T(2) * c0;
+      s.v[a][0] = ldb(arr, N.o[a][1]);
+      s.v[a][1] = ldb(arr, N.o[a][2]);
+      s.v[a][2] = ldb(arr, N.o[a][3]);
     } else if (LAP) {
-      const T m1 = C.load(arr_i, P, I, dist, a, -1);
-      const T p1 = C.load(arr_i, P, I, dist, a, +1);
-      lap += (m1 + p1) - T(2) * c0;
+      s.v[a][0] = ldb(arr, N.o[a][1]);
+      s.v[a][1] = ldb(arr, N.o[a][2]);
     }
   }
 }
 
-template <typename T>
-__device__ __forceinline__ bool cell_of(const StepParams& P, Cell<T>& C) {
-  const long long tile = xcd_tile(blockIdx.x, P.tiles_per_xcd);
-  if (tile >= P.ntiles) return false;
-  const int tx = static_cast<int>(tile % P.ntx);
-  const long long r1 = tile / P.ntx;
-  const int ty = static_cast<int>(r1 % P.nty);
-  const int z = static_cast<int>(r1 / P.nty);
-  const int x = tx * P.tile_x + static_cast<int>(threadIdx.x) % P.tile_x;
-  const int y = ty * P.tile_y + static_cast<int>(threadIdx.x) / P.tile_x;
-  if (x >= P.nx || y >= P.ny) return false;
-  C.x[0] = x;
-  C.x[1] = y;
-  C.x[2] = z;
-  C.n[0] = P.nx;
-  C.n[1] = P.ny;
-  C.n[2] = P.nz;
-  C.stride[0] = 1;
-  C.stride[1] = P.nx;
-  C.stride[2] = static_cast<long long>(P.nx) * P.ny;
-  C.c = x + static_cast<long long>(P.nx) * (y + static_cast<long long>(P.ny) * z);
-  bool in = true;
+// delta t * (flux divergence) and the sum of the axis neighbours used by the
+// Laplacian (without the -2 f(x) per axis) of population I from its stencil.
+template <typename T, int ACT, int I, bool LAP>
+__device__ __forceinline__ void stream_terms(const Sten<T>& s, T c0, T dtv, T& dD, T& nsum) {
+  bool first_d = true, first_n = true;
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
-    if (C.n[a] > 1) in = in && C.x[a] >= 2 && C.x[a] < C.n[a] - 2;
-  C.inner = in;
-  return true;
+  for (int a = 0; a < 3; ++a) {
+    if (!axis_on<ACT>(a)) continue;
+    const int ea = vcomp(I, a);
+    T d = T(0), nb = T(0);
+    bool has_d = false, has_n = false;
+    if (ea > 0) {
+      d = (dtv * T(ea)) * dflux_pos(s.v[a][0], s.v[a][1], c0, s.v[a][2]);
+      nb = s.v[a][1] + s.v[a][2];
+      has_d = true;
+      has_n = LAP;
+    } else if (ea < 0) {
+      d = (dtv * T(ea)) * dflux_neg(s.v[a][0], c0, s.v[a][1], s.v[a][2]);
+      nb = s.v[a][0] + s.v[a][1];
+      has_d = true;
+      has_n = LAP;
+    } else if (LAP) {
+      nb = s.v[a][0] + s.v[a][1];
+      has_n = true;
+    }
+    if (has_d) {
+      dD = first_d ? d : dD + d;
+      first_d = false;
+    }
+    if (has_n) {
+      nsum = first_n ? nb : nsum + nb;
+      first_n = false;
+    }
+  }
+  if (first_d) dD = T(0);
+  if (first_n) nsum = T(0);
+}
+
+// Cell of this thread (see StepParams::order); false if outside the grid.
+__device__ __forceinline__ bool cell_of(const StepParams& P, int& x, int& y, int& z) {
+  const unsigned b = blockIdx.x;
+  const long long l = b / kXcds;
+  const int xcd = static_cast<int>(b % kXcds);
+  const int tiles_pp = P.pw * P.ph;  // tiles per pencil plane
+  const int npx = P.ntx / P.pw;
+  int tx, ty;
+  if (P.order == 1) {
+    const int tin = static_cast<int>(l % tiles_pp);
+    const long long r = l / tiles_pp;
+    const int zl = static_cast<int>(r % P.zslab);
+    const long long pencil = r / P.zslab;
+    tx = static_cast<int>(pencil % npx) * P.pw + tin % P.pw;
+    ty = static_cast<int>(pencil / npx) * P.ph + tin / P.pw;
+    z = xcd * P.zslab + zl;
+    if (ty >= P.nty || z >= P.nz) return false;
+  } else {
+    const long long g = xcd * P.tiles_per_xcd + l;
+    if (g >= P.ntiles) return false;
+    const int tin = static_cast<int>(g % tiles_pp);
+    const long long r = g / tiles_pp;
+    const long long npy = P.nty / P.ph;
+    const int pyi = static_cast<int>(r % npy);
+    const long long r2 = r / npy;
+    z = static_cast<int>(r2 % P.nz);
+    const int pxi = static_cast<int>(r2 / P.nz);
+    tx = pxi * P.pw + tin % P.pw;
+    ty = pyi * P.ph + tin / P.pw;
+  }
+  x = tx * P.tile_x + static_cast<int>(threadIdx.x) % P.tile_x;
+  y = ty * P.tile_y + static_cast<int>(threadIdx.x) / P.tile_x;
+  return x < P.nx && y < P.ny;
 }
 
 // Wavefront-aggregated counter increment.
@@ -317,8 +403,8 @@ __device__ __forceinline__ void count_events(unsigned long long* ctr, bool fired
   if (lane == leader) atomicAdd(ctr, static_cast<unsigned long long>(__popcll(mask)));
 }
 
-// Guard (off unless P.guard): projected fields of new moments and the blend
-// factors for f and h; returns true if either factor is below 1.
+// Guard (decided in FP64): projected fields of the new moments and blend
+// factors for f and h; true if either factor is below 1.
 template <bool WH>
 __device__ __forceinline__ bool guard_eval(const StepParams& P, double E, double Mx, double My,
                                            double Mz, double N0, double& thf, double& thh,
@@ -350,19 +436,19 @@ __device__ __forceinline__ bool guard_eval(const StepParams& P, double E, double
   return th < 1.0 || thh < 1.0;
 }
 
-template <typename T, bool WH>
-__device__ __forceinline__ void moments_of(const T* v_f, const T* v_h, const StepParams& P,
-                                           double& E, double& Mx, double& My, double& Mz,
-                                           double& N0) {
+// FP64 moments of 19 (+19) values in canonical order.
+template <typename T, bool WH, typename LF, typename LH>
+__device__ __forceinline__ void moments64(const StepParams& P, LF&& fval, LH&& hval, double& E,
+                                          double& Mx, double& My, double& Mz, double& N0) {
   double s0 = 0.0, sx = 0.0, sy = 0.0, sz = 0.0, sh = 0.0;
   static_for<0, Q>([&](auto I) {
     constexpr Vel e = vel(I);
-    const double v = static_cast<double>(v_f[I]);
+    const double v = static_cast<double>(fval(I));
     s0 += v;
     if constexpr (e.x != 0) sx += double(e.x) * v;
     if constexpr (e.y != 0) sy += double(e.y) * v;
     if constexpr (e.z != 0) sz += double(e.z) * v;
-    if constexpr (WH) sh += static_cast<double>(v_h[I]);
+    if constexpr (WH) sh += static_cast<double>(hval(I));
   });
   E = P.r * P.r * s0;
   Mx = P.rca * sx;
@@ -371,34 +457,69 @@ __device__ __forceinline__ void moments_of(const T* v_f, const T* v_h, const Ste
   N0 = P.r * sh;
 }
 
+// Per-dimensionality tuning (measured on MI355X): populations gathered per
+// batch, and the minimum waves per SIMD the register allocator must allow.
+#ifndef RLB_BATCH_3D
+#define RLB_BATCH_3D 1
+#endif
+#ifndef RLB_BATCH_2D
+#define RLB_BATCH_2D 3
+#endif
+#ifndef RLB_BATCH_1D
+#define RLB_BATCH_1D 2
+#endif
+#ifndef RLB_OCC_F32
+#define RLB_OCC_F32 3
+#endif
+#ifndef RLB_OCC_F64
+#define RLB_OCC_F64 2
+#endif
+template <typename T>
+struct Occ {
+  static constexpr int value = sizeof(T) == 4 ? RLB_OCC_F32 : RLB_OCC_F64;
+};
+template <int ACT>
+struct Batch {
+  static constexpr int value = ACT == 7 ? RLB_BATCH_3D : (ACT == 3 ? RLB_BATCH_2D : RLB_BATCH_1D);
+  static constexpr int count = (Q + value - 1) / value;
+};
+
 // ---------------------------------------------------------------------------
 // Fused step: moments -> FP64 recovery -> equilibria -> limited streaming,
-// bulk term and implicit collision (Eq. (57)) -> guard -> store.
+// bulk term and implicit collision (Eq. (57)) or Euler update -> guard.
 // ---------------------------------------------------------------------------
 template <typename T, int ACT, bool WH, bool EULER>
-__global__ __launch_bounds__(kBlock) void k_step(const StepParams P) {
-  Cell<T> C;
-  if (!cell_of<T>(P, C)) return;
-  const long long N = P.ncell;
-  const long long c = C.c;
-  const T* __restrict__ fin = static_cast<const T*>(P.f_in);
-  const T* __restrict__ hin = static_cast<const T*>(P.h_in);
-  T* __restrict__ fout = static_cast<T*>(P.f_out);
-  T* __restrict__ hout = static_cast<T*>(P.h_out);
+__global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
+    const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ hin,
+    T* __restrict__ hout, double* __restrict__ hist, const uint8_t* __restrict__ obst,
+    const StepParams P) {
+  int x, y, z;
+  if (!cell_of(P, x, y, z)) return;
+  const long long S = P.pstride;
+  Nbr<ACT> N;
+  make_nbr<T, ACT>(P, x, y, z, N);
+  const unsigned cb = N.c;                                  // byte offset of the cell
+  const unsigned cd = (cb / sizeof(T)) * 8u;                // byte offset in FP64 arrays
+  const long long NC = P.ncell;
+  const double* __restrict__ h0 = hist;
+  const double* __restrict__ h1 = hist + NC;
+  const double* __restrict__ h2 = hist + 2 * NC;
+  const double* __restrict__ h3 = hist + 3 * NC;
+  const double* __restrict__ h4 = hist + 4 * NC;
 
   // Obstacle cells: held at the equilibrium of their prescribed fields.
-  if (P.obst != nullptr && P.obst[c] != 0) {
-    const double eps = P.hist[c], ux = P.hist[N + c], uy = P.hist[2 * N + c],
-                 uz = P.hist[3 * N + c], nn = P.hist[4 * N + c];
+  if (obst != nullptr && obst[cb / sizeof(T)] != 0) {
+    const double eps = ldb(h0, cd), ux = ldb(h1, cd), uy = ldb(h2, cd), uz = ldb(h3, cd),
+                 nn = ldb(h4, cd);
     const double g2 = 1.0 / (1.0 - (ux * ux + uy * uy + uz * uz));
     double K[10];
     feq_coeffs(P, eps, ux, uy, uz, g2, K);
-    static_for<0, Q>([&](auto I) { fout[I * N + c] = static_cast<T>(weight(I) * bracket<I>(K)); });
+    static_for<0, Q>([&](auto I) { stb(fout + I * S, cb, static_cast<T>(weight(I) * bracket<I>(K))); });
     if constexpr (WH) {
       double H[10];
       heq_coeffs(P, nn, ux, uy, uz, sqrt(g2), H);
       static_for<0, Q>(
-          [&](auto I) { hout[I * N + c] = static_cast<T>(wprime(P, I) * bracket<I>(H)); });
+          [&](auto I) { stb(hout + I * S, cb, static_cast<T>(wprime<I>(P) * bracket<I>(H))); });
     }
     return;
   }
@@ -406,134 +527,200 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepParams P) {
   T fc[Q];
   T hc[Q];
   static_for<0, Q>([&](auto I) {
-    fc[I] = fin[I * N + c];
-    if constexpr (WH) hc[I] = hin[I * N + c];
+    fc[I] = ldb(fin + I * S, cb);
+    if constexpr (WH) hc[I] = ldb(hin + I * S, cb);
   });
 
   const T dtv = static_cast<T>(P.dtv);
-  const T kap = static_cast<T>(P.kappa);
+  constexpr T NA2 = T(2 * n_axes<ACT>());
+  // the stencils of a batch of populations (f and h) are gathered first so
+  // that their loads are in flight together
+  constexpr int kBatch = Batch<ACT>::value;
+  constexpr int kNumBatches = Batch<ACT>::count;
 
   if constexpr (EULER) {
     // Streaming and bulk term without collision, then f := f^eq of the
     // post-streaming moments (Sec. III, inviscid case).
-    T fs[Q];
-    T hs[Q];
-    static_for<0, Q>([&](auto I) {
-      T dD, lap;
-      stream_terms<T, ACT, I, (I != 0)>(fin + I * N, P, C, 0, fc[I], dtv, dD, lap);
-      fs[I] = fc[I] - dD + kap * lap;
-      if constexpr (WH) {
-        T dH, lh;
-        stream_terms<T, ACT, I, false>(hin + I * N, P, C, 1, hc[I], dtv, dH, lh);
-        hs[I] = hc[I] - dH;
-      }
+    const T kap = static_cast<T>(P.kappa);
+    static_for<0, kNumBatches>([&](auto g) {
+      Sten<T> sf[kBatch], sh[kBatch];
+      static_for<0, kBatch>([&](auto k) {
+        constexpr int I = g * kBatch + k;
+        if constexpr (I < Q) {
+          gather<T, ACT, I, (I != 0)>(fin + I * S, N, sf[k]);
+          if constexpr (WH) gather<T, ACT, I, false>(hin + I * S, N, sh[k]);
+        }
+      });
+      static_for<0, kBatch>([&](auto k) {
+        constexpr int I = g * kBatch + k;
+        if constexpr (I < Q) {
+          T dD, ns;
+          stream_terms<T, ACT, I, (I != 0)>(sf[k], fc[I], dtv, dD, ns);
+          if constexpr (I != 0) fc[I] = (fc[I] - dD) + kap * (ns - NA2 * fc[I]);
+          else fc[I] = fc[I] - dD;
+          if constexpr (WH) {
+            T dH, nh;
+            stream_terms<T, ACT, I, false>(sh[k], hc[I], dtv, dH, nh);
+            hc[I] = hc[I] - dH;
+          }
+        }
+      });
     });
     double E, Mx, My, Mz, N0;
-    moments_of<T, WH>(fs, hs, P, E, Mx, My, Mz, N0);
+    moments64<T, WH>(P, [&](auto I) { return fc[I]; }, [&](auto I) { return hc[I]; }, E, Mx, My,
+                     Mz, N0);
     Fields F;
-    bool ok;
+    bool ok = true;
     bool fired = false;
     if (P.guard) {
       double thf, thh;
       fired = guard_eval<WH>(P, E, Mx, My, Mz, N0, thf, thh, F);
-      ok = true;
-      if (!fired) ok = recover<WH>(E, Mx, My, Mz, N0, F);
-    } else {
-      ok = recover<WH>(E, Mx, My, Mz, N0, F);
+      count_events(P.guard_count, fired);
     }
-    if (P.guard) count_events(P.guard_count, fired);
+    if (!fired) ok = recover<WH>(E, Mx, My, Mz, N0, F);
     if (!ok) atomicMin(P.bad_step, static_cast<unsigned long long>(P.step_index));
     double K[10];
     feq_coeffs(P, F.eps, F.ux, F.uy, F.uz, F.g2, K);
-    static_for<0, Q>([&](auto I) { fout[I * N + c] = static_cast<T>(weight(I) * bracket<I>(K)); });
+    T Kt[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) Kt[k] = static_cast<T>(K[k]);
+    static_for<0, Q>(
+        [&](auto I) { stb(fout + I * S, cb, static_cast<T>(weight(I)) * bracket<I>(Kt)); });
     if constexpr (WH) {
       double H[10];
       heq_coeffs(P, F.n, F.ux, F.uy, F.uz, F.gam, H);
+      T Ht[10];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) Ht[k] = static_cast<T>(H[k]);
       static_for<0, Q>(
-          [&](auto I) { hout[I * N + c] = static_cast<T>(wprime(P, I) * bracket<I>(H)); });
+          [&](auto I) { stb(hout + I * S, cb, static_cast<T>(wprime<I>(P)) * bracket<I>(Ht)); });
     }
     return;
   } else {
+    const double pe = ldb(h0, cd), pux = ldb(h1, cd), puy = ldb(h2, cd), puz = ldb(h3, cd),
+                 pn = ldb(h4, cd);
     // 1-2: moments and fields at time t.
     double E, Mx, My, Mz, N0;
-    moments_of<T, WH>(fc, hc, P, E, Mx, My, Mz, N0);
+    moments64<T, WH>(P, [&](auto I) { return fc[I]; }, [&](auto I) { return hc[I]; }, E, Mx, My,
+                     Mz, N0);
     Fields F;
     const bool ok = recover<WH>(E, Mx, My, Mz, N0, F);
     if (!ok) atomicMin(P.bad_step, static_cast<unsigned long long>(P.step_index));
 
-    // 3: equilibrium source 2 f^eq(t) - f^eq(t - dt) as one coefficient set.
-    const double pe = P.hist[c], pux = P.hist[N + c], puy = P.hist[2 * N + c],
-                 puz = P.hist[3 * N + c], pn = P.hist[4 * N + c];
+    // 3: the source omega (2 f^eq(t) - f^eq(t - dt)) / (1 + omega) as one
+    // coefficient set, computed in FP64 and rounded once to T.
+    const double omega = P.omega_c / tau_of<T, WH>(P, F);
+    const double inv1p = 1.0 / (1.0 + omega);
+    const double src = omega * inv1p;
     const double pg2 = 1.0 / (1.0 - (pux * pux + puy * puy + puz * puz));
-    double K[10], Kp[10];
-    feq_coeffs(P, F.eps, F.ux, F.uy, F.uz, F.g2, K);
-    feq_coeffs(P, pe, pux, puy, puz, pg2, Kp);
+    T Kt[10];
+    {
+      double K[10], Kp[10];
+      feq_coeffs(P, F.eps, F.ux, F.uy, F.uz, F.g2, K);
+      feq_coeffs(P, pe, pux, puy, puz, pg2, Kp);
 #pragma unroll
-    for (int k = 0; k < 10; ++k) K[k] = 2.0 * K[k] - Kp[k];
-    double H[10];
+      for (int k = 0; k < 10; ++k) Kt[k] = static_cast<T>(src * (2.0 * K[k] - Kp[k]));
+    }
+    T Ht[10];
     if constexpr (WH) {
-      double Hp[10];
+      double H[10], Hp[10];
       heq_coeffs(P, F.n, F.ux, F.uy, F.uz, F.gam, H);
       heq_coeffs(P, pn, pux, puy, puz, sqrt(pg2), Hp);
 #pragma unroll
-      for (int k = 0; k < 10; ++k) H[k] = 2.0 * H[k] - Hp[k];
+      for (int k = 0; k < 10; ++k) Ht[k] = static_cast<T>(src * (2.0 * H[k] - Hp[k]));
     }
-    const double omega = P.omega_c / tau_of<WH>(P, F);
-    const double inv1p = 1.0 / (1.0 + omega);
-    const T tinv = static_cast<T>(inv1p);
+    double* __restrict__ w0 = hist;
+    stb(w0, cd, F.eps);
+    stb(w0 + NC, cd, F.ux);
+    stb(w0 + 2 * NC, cd, F.uy);
+    stb(w0 + 3 * NC, cd, F.uz);
+    stb(w0 + 4 * NC, cd, F.n);
 
-    // 4-5: limited streaming, bulk term (f only, lambda_0 = 0), implicit
-    // collision, Eq. (57).
-    T fn[Q];
-    T hn[Q];
-    static_for<0, Q>([&](auto I) {
-      T dD, lap;
-      stream_terms<T, ACT, I, (I != 0)>(fin + I * N, P, C, 0, fc[I], dtv, dD, lap);
-      const T src = static_cast<T>(omega * (weight(I) * bracket<I>(K)));
-      fn[I] = ((fc[I] - dD) + (src + kap * lap)) * tinv;
-      if constexpr (WH) {
-        T dH, lh;
-        stream_terms<T, ACT, I, false>(hin + I * N, P, C, 1, hc[I], dtv, dH, lh);
-        const T hsrc = static_cast<T>(omega * (wprime(P, I) * bracket<I>(H)));
-        hn[I] = ((hc[I] - dH) + hsrc) * tinv;
-      }
+    const T tinv = static_cast<T>(inv1p);
+    const T kinv = static_cast<T>(P.kappa * inv1p);
+    const T wp[3] = {static_cast<T>(P.wp0), static_cast<T>(P.wp1), static_cast<T>(P.wp2)};
+
+    // 4-5: limited streaming, bulk term (f only, lambda_0 = 0) and implicit
+    // collision, Eq. (57); new moments accumulated for the guard's gate.
+    T gE = T(0), gX = T(0), gY = T(0), gZ = T(0), gN = T(0), gA = T(0), gAh = T(0);
+    static_for<0, kNumBatches>([&](auto g) {
+      Sten<T> sf[kBatch], sh[kBatch];
+      static_for<0, kBatch>([&](auto k) {
+        constexpr int I = g * kBatch + k;
+        if constexpr (I < Q) {
+          gather<T, ACT, I, (I != 0)>(fin + I * S, N, sf[k]);
+          if constexpr (WH) gather<T, ACT, I, false>(hin + I * S, N, sh[k]);
+        }
+      });
+      static_for<0, kBatch>([&](auto k) {
+        constexpr int I = g * kBatch + k;
+        if constexpr (I < Q) {
+          constexpr Vel e = vel(I);
+          T dD, ns;
+          stream_terms<T, ACT, I, (I != 0)>(sf[k], fc[I], dtv, dD, ns);
+          T v = (fc[I] - dD) * tinv + static_cast<T>(weight(I)) * bracket<I>(Kt);
+          if constexpr (I != 0) v += kinv * (ns - NA2 * fc[I]);
+          stb(fout + I * S, cb, v);
+          gE += v;
+          gA += fabs(v);
+          if constexpr (e.x != 0) gX += T(e.x) * v;
+          if constexpr (e.y != 0) gY += T(e.y) * v;
+          if constexpr (e.z != 0) gZ += T(e.z) * v;
+          if constexpr (WH) {
+            T dH, nh;
+            stream_terms<T, ACT, I, false>(sh[k], hc[I], dtv, dH, nh);
+            const T wpi = I == 0 ? wp[0] : (I <= 6 ? wp[1] : wp[2]);
+            const T hv = (hc[I] - dH) * tinv + wpi * bracket<I>(Ht);
+            stb(hout + I * S, cb, hv);
+            gN += hv;
+            gAh += fabs(hv);
+          }
+        }
+      });
     });
 
-    // Guard: blend towards the equilibrium of the projected new moments.
+    // Guard: gate in storage precision with a rounding margin, decide and
+    // blend in FP64 from the stored values.
     if (P.guard) {
-      double E2, Mx2, My2, Mz2, N02;
-      moments_of<T, WH>(fn, hn, P, E2, Mx2, My2, Mz2, N02);
-      double thf, thh;
-      Fields G;
-      const bool fired = guard_eval<WH>(P, E2, Mx2, My2, Mz2, N02, thf, thh, G);
-      if (fired) {
-        double Kg[10];
-        feq_coeffs(P, G.eps, G.ux, G.uy, G.uz, G.g2, Kg);
-        static_for<0, Q>([&](auto I) {
-          const double ge = weight(I) * bracket<I>(Kg);
-          fn[I] = static_cast<T>(ge + thf * (static_cast<double>(fn[I]) - ge));
-        });
-        if constexpr (WH) {
-          double Hg[10];
-          heq_coeffs(P, G.n, G.ux, G.uy, G.uz, G.gam, Hg);
+      constexpr T tol = sizeof(T) == 4 ? T(8e-6) : T(1e-13);
+      const T r2 = static_cast<T>(P.r * P.r), rca = static_cast<T>(P.rca);
+      const T Eg = r2 * gE, mrg = tol * r2 * gA;
+      const T Mg = rca * sqrt(gX * gX + gY * gY + gZ * gZ);
+      bool need = !(Eg > mrg) || (Mg + mrg > static_cast<T>(P.m1) * (Eg - mrg));
+      if constexpr (WH) {
+        const T Ng = static_cast<T>(P.r) * gN;
+        need = need ||
+               !(Ng > static_cast<T>(2.0 * P.efloor * P.gmax) + tol * static_cast<T>(P.r) * gAh);
+      }
+      bool fired = false;
+      if (need) {
+        double E2, Mx2, My2, Mz2, N02;
+        moments64<T, WH>(P, [&](auto I) { return ldb(fout + I * S, cb); },
+                         [&](auto I) { return ldb(hout + I * S, cb); }, E2, Mx2, My2, Mz2, N02);
+        double thf, thh;
+        Fields G;
+        fired = guard_eval<WH>(P, E2, Mx2, My2, Mz2, N02, thf, thh, G);
+        if (fired) {
+          double Kg[10];
+          feq_coeffs(P, G.eps, G.ux, G.uy, G.uz, G.g2, Kg);
           static_for<0, Q>([&](auto I) {
-            const double ge = wprime(P, I) * bracket<I>(Hg);
-            hn[I] = static_cast<T>(ge + thh * (static_cast<double>(hn[I]) - ge));
+            const double ge = weight(I) * bracket<I>(Kg);
+            const double v = static_cast<double>(ldb(fout + I * S, cb));
+            stb(fout + I * S, cb, static_cast<T>(ge + thf * (v - ge)));
           });
+          if constexpr (WH) {
+            double Hg[10];
+            heq_coeffs(P, G.n, G.ux, G.uy, G.uz, G.gam, Hg);
+            static_for<0, Q>([&](auto I) {
+              const double ge = wprime<I>(P) * bracket<I>(Hg);
+              const double v = static_cast<double>(ldb(hout + I * S, cb));
+              stb(hout + I * S, cb, static_cast<T>(ge + thh * (v - ge)));
+            });
+          }
         }
       }
       count_events(P.guard_count, fired);
     }
-
-    static_for<0, Q>([&](auto I) {
-      fout[I * N + c] = fn[I];
-      if constexpr (WH) hout[I * N + c] = hn[I];
-    });
-    P.hist[c] = F.eps;
-    P.hist[N + c] = F.ux;
-    P.hist[2 * N + c] = F.uy;
-    P.hist[3 * N + c] = F.uz;
-    P.hist[4 * N + c] = F.n;
   }
 }
 
@@ -543,36 +730,44 @@ template <typename T, bool WH>
 __global__ __launch_bounds__(kBlock) void k_init(const StepParams P) {
   const long long c = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
   if (c >= P.ncell) return;
-  const long long N = P.ncell;
+  const long long NC = P.ncell, S = P.pstride;
   T* __restrict__ f = static_cast<T*>(P.f_out);
   T* __restrict__ h = static_cast<T*>(P.h_out);
-  const double eps = P.hist[c], ux = P.hist[N + c], uy = P.hist[2 * N + c],
-               uz = P.hist[3 * N + c];
+  const double eps = P.hist[c], ux = P.hist[NC + c], uy = P.hist[2 * NC + c],
+               uz = P.hist[3 * NC + c];
   const double g2 = 1.0 / (1.0 - (ux * ux + uy * uy + uz * uz));
   double K[10];
   feq_coeffs(P, eps, ux, uy, uz, g2, K);
-  static_for<0, Q>([&](auto I) { f[I * N + c] = static_cast<T>(weight(I) * bracket<I>(K)); });
+  static_for<0, Q>([&](auto I) { f[I * S + c] = static_cast<T>(weight(I) * bracket<I>(K)); });
   if constexpr (WH) {
     double H[10];
-    heq_coeffs(P, P.hist[4 * N + c], ux, uy, uz, sqrt(g2), H);
-    static_for<0, Q>([&](auto I) { h[I * N + c] = static_cast<T>(wprime(P, I) * bracket<I>(H)); });
+    heq_coeffs(P, P.hist[4 * NC + c], ux, uy, uz, sqrt(g2), H);
+    static_for<0, Q>([&](auto I) { h[I * S + c] = static_cast<T>(wprime<I>(P) * bracket<I>(H)); });
   } else {
-    P.hist[4 * N + c] = pow(eps / 3.0, 0.75);
+    P.hist[4 * NC + c] = pow(eps / 3.0, 0.75);
   }
 }
 
-// Equilibria of the six face states: face_eq[s][0][i] = f^eq, [s][1][i] = h^eq.
-__global__ void k_face_eq(const StepParams P, const double* states, double* out) {
+// Face slots: equilibria of the six face states in both ping-pong copies.
+template <typename T>
+__global__ void k_face_slots(const StepParams P, const double* states, T* f0, T* f1, T* h0, T* h1) {
   const int s = threadIdx.x;
-  if (s >= 6) return;
+  if (s >= kFaceSlots) return;
   const double* q = states + 5 * s;
   const double g2 = 1.0 / (1.0 - (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]));
   double K[10], H[10];
   feq_coeffs(P, q[0], q[1], q[2], q[3], g2, K);
   heq_coeffs(P, q[4], q[1], q[2], q[3], sqrt(g2), H);
+  const long long S = P.pstride, at = P.ncell + s;
   static_for<0, Q>([&](auto I) {
-    out[(s * 2 + 0) * Q + I] = weight(I) * bracket<I>(K);
-    out[(s * 2 + 1) * Q + I] = wprime(P, I) * bracket<I>(H);
+    const T fe = static_cast<T>(weight(I) * bracket<I>(K));
+    f0[I * S + at] = fe;
+    f1[I * S + at] = fe;
+    if (h0 != nullptr) {
+      const T he = static_cast<T>(wprime<I>(P) * bracket<I>(H));
+      h0[I * S + at] = he;
+      h1[I * S + at] = he;
+    }
   });
 }
 
@@ -582,25 +777,21 @@ __global__ __launch_bounds__(kBlock) void k_moments(const StepParams P, double* 
                                                      unsigned long long* bad) {
   const long long c = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
   if (c >= P.ncell) return;
-  const long long N = P.ncell;
+  const long long NC = P.ncell, S = P.pstride;
   const T* __restrict__ f = static_cast<const T*>(P.f_in);
   const T* __restrict__ h = static_cast<const T*>(P.h_in);
-  T fc[Q], hc[Q];
-  static_for<0, Q>([&](auto I) {
-    fc[I] = f[I * N + c];
-    if constexpr (WH) hc[I] = h[I * N + c];
-  });
   double E, Mx, My, Mz, N0;
-  moments_of<T, WH>(fc, hc, P, E, Mx, My, Mz, N0);
+  moments64<T, WH>(P, [&](auto I) { return f[I * S + c]; }, [&](auto I) { return h[I * S + c]; },
+                   E, Mx, My, Mz, N0);
   Fields F;
   const bool ok = recover<WH>(E, Mx, My, Mz, N0, F);
   const bool obst = P.obst != nullptr && P.obst[c] != 0;
   if (!ok && !obst) atomicMin(bad, 0ull);
   out[c] = ok ? F.eps : NAN;
-  out[N + c] = ok ? F.ux : NAN;
-  out[2 * N + c] = ok ? F.uy : NAN;
-  out[3 * N + c] = ok ? F.uz : NAN;
-  out[4 * N + c] = ok ? F.n : NAN;
+  out[NC + c] = ok ? F.ux : NAN;
+  out[2 * NC + c] = ok ? F.uy : NAN;
+  out[3 * NC + c] = ok ? F.uz : NAN;
+  out[4 * NC + c] = ok ? F.n : NAN;
 }
 
 // Deterministic domain sums of T^{00}, T^{0a}, N^0: per-block tree sums into
@@ -611,15 +802,11 @@ __global__ __launch_bounds__(kBlock) void k_sums_partial(const StepParams P, dou
   const long long c = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
   double v[5] = {0, 0, 0, 0, 0};
   if (c < P.ncell) {
-    const long long N = P.ncell;
+    const long long S = P.pstride;
     const T* __restrict__ f = static_cast<const T*>(P.f_in);
     const T* __restrict__ h = static_cast<const T*>(P.h_in);
-    T fc[Q], hc[Q];
-    static_for<0, Q>([&](auto I) {
-      fc[I] = f[I * N + c];
-      if constexpr (WH) hc[I] = h[I * N + c];
-    });
-    moments_of<T, WH>(fc, hc, P, v[0], v[1], v[2], v[3], v[4]);
+    moments64<T, WH>(P, [&](auto I) { return f[I * S + c]; }, [&](auto I) { return h[I * S + c]; },
+                     v[0], v[1], v[2], v[3], v[4]);
   }
   for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = v[k];
   __syncthreads();
@@ -653,7 +840,8 @@ template <typename T, int ACT, bool WH, bool EU>
 hipError_t launch_step_t(const StepParams& p, hipStream_t s) {
   const long long nblk = p.tiles_per_xcd * kXcds;
   hipLaunchKernelGGL((k_step<T, ACT, WH, EU>), dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0,
-                     s, p);
+                     s, static_cast<const T*>(p.f_in), static_cast<T*>(p.f_out),
+                     static_cast<const T*>(p.h_in), static_cast<T*>(p.h_out), p.hist, p.obst, p);
   return hipGetLastError();
 }
 
@@ -695,8 +883,16 @@ hipError_t launch_init(const StepParams& p, bool fp64, bool with_h, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_face_eq(const StepParams& p, const double* states, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_face_eq, dim3(1), dim3(64), 0, s, p, states, out);
+hipError_t launch_face_slots(const StepParams& p, bool fp64, const double* states, void* f0, void* f1,
+                             void* h0, void* h1, hipStream_t s) {
+  if (fp64)
+    hipLaunchKernelGGL(k_face_slots<double>, dim3(1), dim3(64), 0, s, p, states,
+                       static_cast<double*>(f0), static_cast<double*>(f1), static_cast<double*>(h0),
+                       static_cast<double*>(h1));
+  else
+    hipLaunchKernelGGL(k_face_slots<float>, dim3(1), dim3(64), 0, s, p, states,
+                       static_cast<float*>(f0), static_cast<float*>(f1), static_cast<float*>(h0),
+                       static_cast<float*>(h1));
   return hipGetLastError();
 }
 
