@@ -122,6 +122,8 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="only run a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -133,6 +135,17 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe_gib > 0:
+        # plain copy of known size: rocprofv3 FETCH_SIZE / WRITE_SIZE of this
+        # kernel calibrate the counters used for the step kernel's traffic
+        n = int(args.copy_probe_gib * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)  # an elementwise shader kernel (copy_ may use a blit)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4}))
+        return
     precision = rlb.RLB_MIXED if args.precision == "mixed" else rlb.RLB_FP64
     w = make_workload(args.workload, precision)
     # a dedicated stream (default priority): the library launches on it and

@@ -292,6 +292,25 @@ __device__ __forceinline__ void stb(T* __restrict__ base, unsigned off, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
 }
 
+// Streaming (non-temporal) accesses for data touched once per step: the new
+// populations and the previous-step fields.  They leave L2 capacity to the
+// stencil halos that neighbouring workgroups re-read.
+#ifndef RLB_STREAMING
+#define RLB_STREAMING 1
+#endif
+template <typename T>
+__device__ __forceinline__ void stb_nt(T* __restrict__ base, unsigned off, T v) {
+  T* p = reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
+  if constexpr (RLB_STREAMING) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+template <typename T>
+__device__ __forceinline__ T ldb_nt(const T* __restrict__ base, unsigned off) {
+  const T* p = reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+  if constexpr (RLB_STREAMING) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
 // Star stencil of one population: per active axis the values the limited
 // flux (and, with LAP, the Laplacian) needs: e^a > 0: x-2, x-1, x+1;
 // e^a < 0: x-1, x+1, x+2; e^a = 0 with LAP: x-1, x+1.
@@ -585,7 +604,7 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
 #pragma unroll
     for (int k = 0; k < 10; ++k) Kt[k] = static_cast<T>(K[k]);
     static_for<0, Q>(
-        [&](auto I) { stb(fout + I * S, cb, static_cast<T>(weight(I)) * bracket<I>(Kt)); });
+        [&](auto I) { stb_nt(fout + I * S, cb, static_cast<T>(weight(I)) * bracket<I>(Kt)); });
     if constexpr (WH) {
       double H[10];
       heq_coeffs(P, F.n, F.ux, F.uy, F.uz, F.gam, H);
@@ -593,12 +612,12 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
 #pragma unroll
       for (int k = 0; k < 10; ++k) Ht[k] = static_cast<T>(H[k]);
       static_for<0, Q>(
-          [&](auto I) { stb(hout + I * S, cb, static_cast<T>(wprime<I>(P)) * bracket<I>(Ht)); });
+          [&](auto I) { stb_nt(hout + I * S, cb, static_cast<T>(wprime<I>(P)) * bracket<I>(Ht)); });
     }
     return;
   } else {
-    const double pe = ldb(h0, cd), pux = ldb(h1, cd), puy = ldb(h2, cd), puz = ldb(h3, cd),
-                 pn = ldb(h4, cd);
+    const double pe = ldb_nt(h0, cd), pux = ldb_nt(h1, cd), puy = ldb_nt(h2, cd),
+                 puz = ldb_nt(h3, cd), pn = ldb_nt(h4, cd);
     // 1-2: moments and fields at time t.
     double E, Mx, My, Mz, N0;
     moments64<T, WH>(P, [&](auto I) { return fc[I]; }, [&](auto I) { return hc[I]; }, E, Mx, My,
@@ -630,11 +649,11 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
       for (int k = 0; k < 10; ++k) Ht[k] = static_cast<T>(src * (2.0 * H[k] - Hp[k]));
     }
     double* __restrict__ w0 = hist;
-    stb(w0, cd, F.eps);
-    stb(w0 + NC, cd, F.ux);
-    stb(w0 + 2 * NC, cd, F.uy);
-    stb(w0 + 3 * NC, cd, F.uz);
-    stb(w0 + 4 * NC, cd, F.n);
+    stb_nt(w0, cd, F.eps);
+    stb_nt(w0 + NC, cd, F.ux);
+    stb_nt(w0 + 2 * NC, cd, F.uy);
+    stb_nt(w0 + 3 * NC, cd, F.uz);
+    stb_nt(w0 + 4 * NC, cd, F.n);
 
     const T tinv = static_cast<T>(inv1p);
     const T kinv = static_cast<T>(P.kappa * inv1p);
@@ -660,7 +679,7 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
           stream_terms<T, ACT, I, (I != 0)>(sf[k], fc[I], dtv, dD, ns);
           T v = (fc[I] - dD) * tinv + static_cast<T>(weight(I)) * bracket<I>(Kt);
           if constexpr (I != 0) v += kinv * (ns - NA2 * fc[I]);
-          stb(fout + I * S, cb, v);
+          stb_nt(fout + I * S, cb, v);
           gE += v;
           gA += fabs(v);
           if constexpr (e.x != 0) gX += T(e.x) * v;
@@ -671,7 +690,7 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
             stream_terms<T, ACT, I, false>(sh[k], hc[I], dtv, dH, nh);
             const T wpi = I == 0 ? wp[0] : (I <= 6 ? wp[1] : wp[2]);
             const T hv = (hc[I] - dH) * tinv + wpi * bracket<I>(Ht);
-            stb(hout + I * S, cb, hv);
+            stb_nt(hout + I * S, cb, hv);
             gN += hv;
             gAh += fabs(hv);
           }

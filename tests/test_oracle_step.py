@@ -362,3 +362,21 @@ def test_all_outflow_3d_reads_no_corner_ghosts():
     o = oracle_for(w)
     assert o.step(5) == 0
     assert all(np.isfinite(a).all() for a in o.fields())
+
+
+def test_guarded_shock_cloud_predictability_horizon():
+    """The guarded shock-cloud run is chaotic: a one-ulp perturbation of the
+    oracle's own input stays below 1e-12 for the 30 steps the GPU parity test
+    uses, and grows by many orders of magnitude over 120 steps."""
+    from tests._helpers import field_errors
+    w = W.shock_cloud_2d(nx=256, ny=128, precision=W.FP64)
+    a = oracle_for(w)
+    wp = w.copy_with()
+    wp.eps = w.eps * (1 + 2.2e-16 * np.random.default_rng(0).choice([-1, 1], w.eps.shape))
+    b = oracle_for(wp)
+    assert a.step(30) == 0 and b.step(30) == 0
+    e30 = field_errors(b.fields(), a.fields())
+    assert max(e30.values()) < 1e-12
+    assert a.step(90) == 0 and b.step(90) == 0
+    e120 = field_errors(b.fields(), a.fields())
+    assert e120["eps"] > 1e3 * max(e30["eps"], 1e-16)
