@@ -1,0 +1,81 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch
+configuration bench.py times: the GPU advances the whole grid; the oracle
+recomputes sampled cells from their dependency cone (crops of radius 2k+2
+around each cell, real boundary conditions where the crop reaches the edge).
+FP64: rel. error <= 1e-10 per sampled field value; mixed precision: the
+per-field bounds of test_gpu_parity."""
+import numpy as np
+import pytest
+
+from paper_1302_1125_amd import workloads as W
+from tests._helpers import crop_workload, sampled_oracle_fields
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 3
+
+
+@pytest.fixture(scope="module")
+def rlb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1302_1125_amd import rlb as R
+    R.load()
+    return R
+
+
+def _sample_cells(w, rng, k=48):
+    nz, ny, nx = w.shape
+    cells = [tuple(int(rng.integers(0, m)) for m in (nz, ny, nx)) for _ in range(k)]
+    # boundaries and corners
+    cells += [(0, 0, 0), (nz - 1, ny - 1, nx - 1), (nz // 2, 0, nx // 2), (nz // 2, ny - 1, 1),
+              (0, ny // 2, nx - 2), (nz - 1, 1, 0)]
+    # cells where the state changes fastest (largest initial gradient of eps)
+    g = np.abs(np.diff(np.log(w.eps), axis=-1))
+    flat = np.argsort(g.ravel())[-16:]
+    for f in flat:
+        z, y, x = np.unravel_index(f, g.shape)
+        cells.append((int(z), int(y), int(x)))
+    return cells
+
+
+def _compare(R, w, precision, tol):
+    print(f"[gpu-case] full-size {w.name} {w.nx}x{w.ny}x{w.nz} precision={precision} steps={STEPS}", flush=True)
+    ctx = R.context_for_workload(w, precision=precision)
+    ctx.rlb_step(STEPS)
+    g = ctx.rlb_moments()
+    ctx.close()
+    rng = np.random.default_rng(99)
+    cells = _sample_cells(w, rng)
+    ref = sampled_oracle_fields(w, cells, STEPS)
+    got = np.array([[float(a[c]) for a in g] for c in cells])
+    # eps and n relative to themselves; velocities relative to 1 (|u| < 1)
+    scale = np.maximum(np.abs(ref), 1e-300)
+    scale[:, 1:4] = 1.0
+    err = np.abs(got - ref) / scale
+    worst = err.max(axis=0)
+    print("max rel. error per field (eps, ux, uy, uz, n):", worst)
+    assert np.all(np.isfinite(got))
+    for k, name in enumerate(("eps", "ux", "uy", "uz", "n")):
+        assert worst[k] <= tol[name], (name, worst[k])
+
+
+FP64_TOL = {k: 1e-10 for k in ("eps", "ux", "uy", "uz", "n")}
+MIXED_TOL = {"eps": 2e-5, "ux": 2e-5, "uy": 2e-5, "uz": 2e-5, "n": 2e-5}
+
+
+def test_blast_wave_384_mixed(rlb):
+    _compare(rlb, W.blast_wave_3d(precision=W.MIXED), W.MIXED, MIXED_TOL)
+
+
+def test_blast_wave_384_fp64(rlb):
+    _compare(rlb, W.blast_wave_3d(precision=W.FP64), W.FP64, FP64_TOL)
+
+
+def test_shock_cloud_2048_mixed(rlb):
+    _compare(rlb, W.shock_cloud_2d(precision=W.MIXED), W.MIXED, MIXED_TOL)
+
+
+def test_shock_cloud_2048_fp64(rlb):
+    _compare(rlb, W.shock_cloud_2d(precision=W.FP64), W.FP64, FP64_TOL)
