@@ -172,6 +172,87 @@ const char* rlb_last_error(void);
    invalid).  Used for memory-based admission. */
 uint64_t rlb_footprint_bytes(const rlb_config* cfg);
 
+/* ------------------------------------------------------------------------
+ * Batched serving of many independent 1D solves (segment step).
+ *
+ * A server owns one device arena and a worker thread that runs a continuous
+ * batching loop: requests submitted at any time are admitted as soon as an
+ * arena range of their footprint and a slot are free (first fit, FIFO with
+ * backfill); every resident request is advanced by the same fused launches
+ * (one launch per step covers all of them, each with its own size, steps,
+ * eta/s, alpha and end states), chained in hipGraph chunks of chunk_steps
+ * steps; a request whose steps are done is read back (fields as in
+ * rlb_moments) and its memory is freed for the next one.  The per-cell
+ * arithmetic is the update of rlb_step (Sec. II.A, Eq. (57)), so a request's
+ * result does not depend on which other requests share the launches.
+ * ---------------------------------------------------------------------- */
+typedef struct rlb_server rlb_server; /* opaque */
+
+typedef struct {
+  uint32_t struct_size;  /* = sizeof(rlb_request)                            */
+  int32_t n;             /* cells, >= 4                                      */
+  int64_t steps;         /* steps to take, >= 0                              */
+  const double* eps;     /* initial fields, length n; copied at submission   */
+  const double* ux;
+  const double* uy;
+  const double* uz;
+  const double* dens;    /* required iff the server carries the density      */
+  double eta_over_s;     /* used when the server's tau_mode is ETA_OVER_S    */
+  double tau;            /* used when tau_mode is UNIFORM; > 0               */
+  double alpha;          /* bulk constant, >= 0                              */
+  int32_t bc_lo, bc_hi;  /* RLB_BC_* of the two ends (periodic in pairs)      */
+  double face_lo[5];     /* (eps, ux, uy, uz, n) of a FIXED end               */
+  double face_hi[5];
+} rlb_request;
+
+typedef struct {
+  uint64_t submitted, admitted, completed, failed, rejected;
+  uint64_t capacity_cells;          /* arena size                            */
+  uint64_t resident_cells_peak;     /* most arena cells in use at once        */
+  uint64_t resident_requests_peak;
+  uint64_t chunks;                  /* graph launches                          */
+  uint64_t global_steps;            /* steps of the batched loop               */
+  double cell_updates;              /* sum of n * steps over completed        */
+  double busy_seconds;              /* wall time with resident work            */
+  double wall_seconds;              /* first submission to last completion    */
+  double latency_p50, latency_p99, latency_max; /* s, submission -> result  */
+} rlb_server_stats;
+
+/* Create a server.  From *common only precision, collision, tau_mode,
+   with_density, nu, dt_over_dx and the guard fields are used (grid, bc, tau,
+   eta_over_s and alpha are per request).  budget_bytes: device memory of the
+   arena (populations, ping-pong, previous fields); chunk_steps: steps per
+   graph launch, even, >= 2.  The server runs on a stream it creates. */
+rlb_status rlb_server_create(const rlb_config* common, uint64_t budget_bytes, int32_t chunk_steps,
+                             rlb_server** out);
+
+/* Queue a request (inputs are copied; returns at once).  RLB_E_OUT_OF_MEMORY
+   if it can never fit the arena, RLB_E_INADMISSIBLE for inadmissible fields,
+   RLB_E_INVALID_ARG for bad sizes or parameters. */
+rlb_status rlb_server_submit(rlb_server* srv, const rlb_request* req, uint64_t* id);
+
+/* Non-blocking: *done = 1 when the request's result is ready. */
+rlb_status rlb_server_poll(rlb_server* srv, uint64_t id, int32_t* done);
+
+/* Block until the request is done, copy its fields (any pointer may be NULL)
+   and release it.  latency_s: submission -> result ready on the host;
+   first_bad: first inadmissible local step or -1; guard_events: its count.
+   Returns RLB_E_INADMISSIBLE (fields still copied) if a step was inadmissible. */
+rlb_status rlb_server_result(rlb_server* srv, uint64_t id, double* eps, double* ux, double* uy,
+                             double* uz, double* n, double* latency_s, int64_t* first_bad,
+                             int64_t* guard_events);
+
+/* Block until every submitted request is done. */
+rlb_status rlb_server_drain(rlb_server* srv);
+
+rlb_status rlb_server_stats_get(rlb_server* srv, rlb_server_stats* out);
+
+/* Stop the loop (pending requests fail) and free everything.  NULL: no-op. */
+void rlb_server_destroy(rlb_server* srv);
+
+/* Arena bytes one request of n cells occupies in a server with *common. */
+uint64_t rlb_request_footprint_bytes(const rlb_config* common, int32_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librlb.so")
-SOURCES = [os.path.join(CSRC, "rlb_kernels.hip"), os.path.join(CSRC, "rlb_api.cpp")]
+SOURCES = [os.path.join(CSRC, "rlb_kernels.hip"), os.path.join(CSRC, "rlb_api.cpp"),
+           os.path.join(CSRC, "rlb_server.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -18,6 +19,7 @@ FLAGS = [
     # packed FP32 instructions stay off (compiler-generated only on request)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
+    "-pthread",
 ]
 
 

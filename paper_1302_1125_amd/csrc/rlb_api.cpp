@@ -141,6 +141,8 @@ rlb_status dalloc(P** p, size_t bytes, const char* what) {
   return RLB_OK;
 }
 
+void fill_constants(const rlb_config& c, rlb::StepParams& p);
+
 int largest_divisor_at_most(int n, int cap) {
   for (int d = cap < n ? cap : n; d > 1; --d)
     if (n % d == 0) return d;
@@ -190,6 +192,25 @@ void fill_params(rlb_ctx* x) {
     p.tiles_per_xcd = (p.ntiles + rlb::kXcds - 1) / rlb::kXcds;
   }
   for (int k = 0; k < 6; ++k) p.bc[k] = c.bc[k];
+  fill_constants(c, p);
+  p.hist = x->hist;
+  p.obst = nullptr;
+  p.cell0 = 0;
+  p.range = x->ncell;
+  p.bad_step = x->counters;
+  p.guard_count = x->counters + 1;
+}
+
+}  // namespace
+
+// Lattice and run constants of a configuration (shared with the server).
+void rlb_fill_constants(const rlb_config& c, rlb::StepParams& p) { fill_constants(c, p); }
+rlb_status rlb_validate_config(const rlb_config* c) { return validate(c); }
+rlb_status rlb_set_error(rlb_status s, const std::string& msg) { return fail(s, msg); }
+
+namespace {
+
+void fill_constants(const rlb_config& c, rlb::StepParams& p) {
   const double nu = c.nu;
   p.a_scale = nu * nu / 27.0;
   p.r = std::sqrt(27.0) / nu;
@@ -215,10 +236,6 @@ void fill_params(rlb_ctx* x) {
     p.efloor = c.guard_efloor;
     p.gmax = 1.0 / std::sqrt((1.0 - um) * (1.0 + um));
   }
-  p.hist = x->hist;
-  p.obst = nullptr;
-  p.bad_step = x->counters;
-  p.guard_count = x->counters + 1;
 }
 
 rlb_status check_ctx(rlb_ctx* x) {

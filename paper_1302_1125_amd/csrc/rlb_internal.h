@@ -70,6 +70,31 @@ struct StepParams {
   unsigned long long* bad_step;    // atomicMin of the first inadmissible step
   unsigned long long* guard_count; // cell-steps blended by the guard
   long long step_index;
+  // Segment mode (many independent 1D domains in one arena, see SegDesc):
+  const struct SegDesc* segs;  // device segment table
+  const int2* tiles;           // per workgroup: (segment id or -1, tile within segment)
+  const long long* gstep;      // device: global step at the start of the chunk
+  int step_in_chunk;           // offset of this launch within the chunk
+  long long cell0;             // first cell of k_init / k_moments ranges
+  long long range;             // number of cells of k_init / k_moments ranges (0: ncell)
+};
+
+// One independent 1D domain of the batched segment step.  Its cells occupy
+// arena indices [base, base + n + 2): a left ghost, n interior cells, a right
+// ghost.  Ghosts hold the equilibria of FIXED end states (written once); other
+// boundary conditions are folded into the neighbour indices.
+struct SegDesc {
+  long long base;
+  long long start;   // global step at which the segment takes its first step
+  long long steps;   // steps to take; afterwards the kernel copies it forward
+  int n;
+  int bc_lo, bc_hi;
+  int id;            // slot of the per-segment counters
+  double nu2_etas;   // nu^2 eta/s of this request
+  double kappa;      // omega_c * alpha of this request
+  double tau;        // uniform relaxation time of this request
+  unsigned long long* bad;    // [slots] first inadmissible local step
+  unsigned long long* guard;  // [slots] guard events
 };
 
 // Launchers (rlb_kernels.hip).  Return hipSuccess or the launch error.
@@ -82,5 +107,12 @@ hipError_t launch_moments(const StepParams& p, bool fp64, bool with_h, double* o
                           unsigned long long* bad_flag, hipStream_t s);
 hipError_t launch_sums(const StepParams& p, bool fp64, bool with_h, double* partial, int nblocks,
                        double* out5, hipStream_t s);
+// Batched segment step over `grid` workgroups (p.tiles has >= grid entries).
+hipError_t launch_seg_step(const StepParams& p, bool fp64, bool with_h, bool euler, unsigned grid,
+                           hipStream_t s);
+// Equilibria of a segment's two end states into its ghost cells (both copies).
+hipError_t launch_seg_ghosts(const StepParams& p, bool fp64, long long lo_cell, long long hi_cell,
+                             const double* states_dev /*2 x 5*/, void* f0, void* f1, void* h0,
+                             void* h1, hipStream_t s);
 
 }  // namespace rlb

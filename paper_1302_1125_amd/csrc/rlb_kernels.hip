@@ -195,12 +195,13 @@ __device__ __forceinline__ bool recover(double E, double Mx, double My, double M
 #define RLB_TAU_F64 0
 #endif
 template <typename T, bool WH>
-__device__ __forceinline__ double tau_of(const StepParams& P, const Fields& F) {
-  if (P.tau_mode == 0) return P.tau;
+__device__ __forceinline__ double tau_of(const StepParams& P, const Fields& F, double tau_u,
+                                         double nu2_etas) {
+  if (P.tau_mode == 0) return tau_u;
   if constexpr (sizeof(T) == 4 && !RLB_TAU_F64) {
     const float eps = static_cast<float>(F.eps), n = static_cast<float>(F.n);
     const float p = eps * (1.0f / 3.0f);
-    const float c = static_cast<float>(P.nu2_etas);
+    const float c = static_cast<float>(nu2_etas);
     if constexpr (WH) {
       // ln lambda = ln n - 3 ln T = 4 ln n - 3 ln p (no overflow of T^3)
       const float s = n * (4.0f - (4.0f * __logf(n) - 3.0f * __logf(p)));
@@ -214,9 +215,9 @@ __device__ __forceinline__ double tau_of(const StepParams& P, const Fields& F) {
       const double T_ = p / F.n;
       const double lam = F.n / (T_ * T_ * T_);
       const double s = F.n * (4.0 - log(lam));
-      return 0.5 + P.nu2_etas * s / (F.eps + p);
+      return 0.5 + nu2_etas * s / (F.eps + p);
     } else {
-      return 0.5 + P.nu2_etas / sqrt(sqrt(p));
+      return 0.5 + nu2_etas / sqrt(sqrt(p));
     }
   }
 }
@@ -279,6 +280,27 @@ __device__ __forceinline__ void make_nbr(const StepParams& P, int x, int y, int 
       }
       N.o[a][j] = static_cast<unsigned>(idx) * static_cast<unsigned>(sizeof(T));
     }
+  }
+}
+
+// Neighbour byte offsets of interior cell `local` of a batched 1D segment
+// (arena layout of SegDesc: ghost, n cells, ghost).
+template <typename T>
+__device__ __forceinline__ void make_seg_nbr(const SegDesc& sd, int local, Nbr<1>& N) {
+  const long long c = sd.base + 1 + local;
+  N.c = static_cast<unsigned>(c) * static_cast<unsigned>(sizeof(T));
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = j < 2 ? j - 2 : j - 1;
+    const int q = local + k;
+    long long idx = c + k;
+    if (q < 0) {
+      idx = sd.bc_lo == kBcFixed ? sd.base : (sd.bc_lo == kBcPeriodic ? c + k + sd.n : sd.base + 1);
+    } else if (q >= sd.n) {
+      idx = sd.bc_hi == kBcFixed ? sd.base + 1 + sd.n
+                                 : (sd.bc_hi == kBcPeriodic ? c + k - sd.n : sd.base + sd.n);
+    }
+    N.o[0][j] = static_cast<unsigned>(idx) * static_cast<unsigned>(sizeof(T));
   }
 }
 
@@ -507,16 +529,46 @@ struct Batch {
 // Fused step: moments -> FP64 recovery -> equilibria -> limited streaming,
 // bulk term and implicit collision (Eq. (57)) or Euler update -> guard.
 // ---------------------------------------------------------------------------
-template <typename T, int ACT, bool WH, bool EULER>
+template <typename T, int ACT, bool WH, bool EULER, bool SEG>
 __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
     const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ hin,
     T* __restrict__ hout, double* __restrict__ hist, const uint8_t* __restrict__ obst,
     const StepParams P) {
-  int x, y, z;
-  if (!cell_of(P, x, y, z)) return;
   const long long S = P.pstride;
   Nbr<ACT> N;
-  make_nbr<T, ACT>(P, x, y, z, N);
+  // run parameters (per request in segment mode)
+  double kappa_d = P.kappa, nu2e = P.nu2_etas, tau_u = P.tau;
+  unsigned long long* bad_ptr = P.bad_step;
+  unsigned long long* guard_ptr = P.guard_count;
+  long long step_idx = P.step_index;
+  if constexpr (SEG) {
+    static_assert(ACT == 1, "segments are one-dimensional");
+    const int2 t = P.tiles[blockIdx.x];
+    if (t.x < 0) return;
+    const SegDesc& sd = P.segs[t.x];
+    const int local = t.y * kBlock + static_cast<int>(threadIdx.x);
+    if (local >= sd.n) return;
+    make_seg_nbr<T>(sd, local, N);
+    const long long ls = *P.gstep + P.step_in_chunk - sd.start;
+    if (ls >= sd.steps) {
+      // finished: carry the state into the other copy until it is retired
+      static_for<0, Q>([&](auto I) {
+        stb_nt(fout + I * S, N.c, ldb(fin + I * S, N.c));
+        if constexpr (WH) stb_nt(hout + I * S, N.c, ldb(hin + I * S, N.c));
+      });
+      return;
+    }
+    kappa_d = sd.kappa;
+    nu2e = sd.nu2_etas;
+    tau_u = sd.tau;
+    bad_ptr = sd.bad + sd.id;
+    guard_ptr = sd.guard + sd.id;
+    step_idx = ls;
+  } else {
+    int x, y, z;
+    if (!cell_of(P, x, y, z)) return;
+    make_nbr<T, ACT>(P, x, y, z, N);
+  }
   const unsigned cb = N.c;                                  // byte offset of the cell
   const unsigned cd = (cb / sizeof(T)) * 8u;                // byte offset in FP64 arrays
   const long long NC = P.ncell;
@@ -527,7 +579,7 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
   const double* __restrict__ h4 = hist + 4 * NC;
 
   // Obstacle cells: held at the equilibrium of their prescribed fields.
-  if (obst != nullptr && obst[cb / sizeof(T)] != 0) {
+  if (!SEG && obst != nullptr && obst[cb / sizeof(T)] != 0) {
     const double eps = ldb(h0, cd), ux = ldb(h1, cd), uy = ldb(h2, cd), uz = ldb(h3, cd),
                  nn = ldb(h4, cd);
     const double g2 = 1.0 / (1.0 - (ux * ux + uy * uy + uz * uz));
@@ -560,7 +612,7 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
   if constexpr (EULER) {
     // Streaming and bulk term without collision, then f := f^eq of the
     // post-streaming moments (Sec. III, inviscid case).
-    const T kap = static_cast<T>(P.kappa);
+    const T kap = static_cast<T>(kappa_d);
     static_for<0, kNumBatches>([&](auto g) {
       Sten<T> sf[kBatch], sh[kBatch];
       static_for<0, kBatch>([&](auto k) {
@@ -594,10 +646,10 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
     if (P.guard) {
       double thf, thh;
       fired = guard_eval<WH>(P, E, Mx, My, Mz, N0, thf, thh, F);
-      count_events(P.guard_count, fired);
+      count_events(guard_ptr, fired);
     }
     if (!fired) ok = recover<WH>(E, Mx, My, Mz, N0, F);
-    if (!ok) atomicMin(P.bad_step, static_cast<unsigned long long>(P.step_index));
+    if (!ok) atomicMin(bad_ptr, static_cast<unsigned long long>(step_idx));
     double K[10];
     feq_coeffs(P, F.eps, F.ux, F.uy, F.uz, F.g2, K);
     T Kt[10];
@@ -624,11 +676,11 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
                      Mz, N0);
     Fields F;
     const bool ok = recover<WH>(E, Mx, My, Mz, N0, F);
-    if (!ok) atomicMin(P.bad_step, static_cast<unsigned long long>(P.step_index));
+    if (!ok) atomicMin(bad_ptr, static_cast<unsigned long long>(step_idx));
 
     // 3: the source omega (2 f^eq(t) - f^eq(t - dt)) / (1 + omega) as one
     // coefficient set, computed in FP64 and rounded once to T.
-    const double omega = P.omega_c / tau_of<T, WH>(P, F);
+    const double omega = P.omega_c / tau_of<T, WH>(P, F, tau_u, nu2e);
     const double inv1p = 1.0 / (1.0 + omega);
     const double src = omega * inv1p;
     const double pg2 = 1.0 / (1.0 - (pux * pux + puy * puy + puz * puz));
@@ -656,7 +708,7 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
     stb_nt(w0 + 4 * NC, cd, F.n);
 
     const T tinv = static_cast<T>(inv1p);
-    const T kinv = static_cast<T>(P.kappa * inv1p);
+    const T kinv = static_cast<T>(kappa_d * inv1p);
     const T wp[3] = {static_cast<T>(P.wp0), static_cast<T>(P.wp1), static_cast<T>(P.wp2)};
 
     // 4-5: limited streaming, bulk term (f only, lambda_0 = 0) and implicit
@@ -738,7 +790,7 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
           }
         }
       }
-      count_events(P.guard_count, fired);
+      count_events(guard_ptr, fired);
     }
   }
 }
@@ -747,8 +799,9 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
 // density the lattice equilibrium density (eps/3)^(3/4) is written to hist.
 template <typename T, bool WH>
 __global__ __launch_bounds__(kBlock) void k_init(const StepParams P) {
-  const long long c = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
-  if (c >= P.ncell) return;
+  const long long r = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (r >= P.range) return;
+  const long long c = P.cell0 + r;
   const long long NC = P.ncell, S = P.pstride;
   T* __restrict__ f = static_cast<T*>(P.f_out);
   T* __restrict__ h = static_cast<T*>(P.h_out);
@@ -794,9 +847,10 @@ __global__ void k_face_slots(const StepParams P, const double* states, T* f0, T*
 template <typename T, bool WH>
 __global__ __launch_bounds__(kBlock) void k_moments(const StepParams P, double* out,
                                                      unsigned long long* bad) {
-  const long long c = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
-  if (c >= P.ncell) return;
-  const long long NC = P.ncell, S = P.pstride;
+  const long long r = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (r >= P.range) return;
+  const long long c = P.cell0 + r;
+  const long long NC = P.range, S = P.pstride;
   const T* __restrict__ f = static_cast<const T*>(P.f_in);
   const T* __restrict__ h = static_cast<const T*>(P.h_in);
   double E, Mx, My, Mz, N0;
@@ -806,11 +860,11 @@ __global__ __launch_bounds__(kBlock) void k_moments(const StepParams P, double* 
   const bool ok = recover<WH>(E, Mx, My, Mz, N0, F);
   const bool obst = P.obst != nullptr && P.obst[c] != 0;
   if (!ok && !obst) atomicMin(bad, 0ull);
-  out[c] = ok ? F.eps : NAN;
-  out[NC + c] = ok ? F.ux : NAN;
-  out[2 * NC + c] = ok ? F.uy : NAN;
-  out[3 * NC + c] = ok ? F.uz : NAN;
-  out[4 * NC + c] = ok ? F.n : NAN;
+  out[r] = ok ? F.eps : NAN;
+  out[NC + r] = ok ? F.ux : NAN;
+  out[2 * NC + r] = ok ? F.uy : NAN;
+  out[3 * NC + r] = ok ? F.uz : NAN;
+  out[4 * NC + r] = ok ? F.n : NAN;
 }
 
 // Deterministic domain sums of T^{00}, T^{0a}, N^0: per-block tree sums into
@@ -858,7 +912,7 @@ __global__ __launch_bounds__(kBlock) void k_sums_final(const double* partial, in
 template <typename T, int ACT, bool WH, bool EU>
 hipError_t launch_step_t(const StepParams& p, hipStream_t s) {
   const long long nblk = p.tiles_per_xcd * kXcds;
-  hipLaunchKernelGGL((k_step<T, ACT, WH, EU>), dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0,
+  hipLaunchKernelGGL((k_step<T, ACT, WH, EU, false>), dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0,
                      s, static_cast<const T*>(p.f_in), static_cast<T*>(p.f_out),
                      static_cast<const T*>(p.h_in), static_cast<T*>(p.h_out), p.hist, p.obst, p);
   return hipGetLastError();
@@ -882,7 +936,63 @@ hipError_t launch_step_p(const StepParams& p, int act, bool with_h, bool euler, 
   }
 }
 
+template <typename T, bool WH, bool EU>
+hipError_t launch_seg_t(const StepParams& p, unsigned grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_step<T, 1, WH, EU, true>), dim3(grid), dim3(kBlock), 0, s,
+                     static_cast<const T*>(p.f_in), static_cast<T*>(p.f_out),
+                     static_cast<const T*>(p.h_in), static_cast<T*>(p.h_out), p.hist, nullptr, p);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_seg_ghosts(const StepParams P, long long lo, long long hi, const double* states,
+                             T* f0, T* f1, T* h0, T* h1) {
+  const int s = threadIdx.x;
+  if (s >= 2) return;
+  const double* q = states + 5 * s;
+  const double g2 = 1.0 / (1.0 - (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]));
+  double K[10], H[10];
+  feq_coeffs(P, q[0], q[1], q[2], q[3], g2, K);
+  heq_coeffs(P, q[4], q[1], q[2], q[3], sqrt(g2), H);
+  const long long S = P.pstride, at = s == 0 ? lo : hi;
+  static_for<0, Q>([&](auto I) {
+    const T fe = static_cast<T>(weight(I) * bracket<I>(K));
+    f0[I * S + at] = fe;
+    f1[I * S + at] = fe;
+    if (h0 != nullptr) {
+      const T he = static_cast<T>(wprime<I>(P) * bracket<I>(H));
+      h0[I * S + at] = he;
+      h1[I * S + at] = he;
+    }
+  });
+}
+
 }  // namespace
+
+hipError_t launch_seg_step(const StepParams& p, bool fp64, bool with_h, bool euler, unsigned grid,
+                           hipStream_t s) {
+  if (grid == 0) return hipSuccess;
+  if (fp64) {
+    if (with_h) return euler ? launch_seg_t<double, true, true>(p, grid, s) : launch_seg_t<double, true, false>(p, grid, s);
+    return euler ? launch_seg_t<double, false, true>(p, grid, s) : launch_seg_t<double, false, false>(p, grid, s);
+  }
+  if (with_h) return euler ? launch_seg_t<float, true, true>(p, grid, s) : launch_seg_t<float, true, false>(p, grid, s);
+  return euler ? launch_seg_t<float, false, true>(p, grid, s) : launch_seg_t<float, false, false>(p, grid, s);
+}
+
+hipError_t launch_seg_ghosts(const StepParams& p, bool fp64, long long lo, long long hi,
+                             const double* states, void* f0, void* f1, void* h0, void* h1,
+                             hipStream_t s) {
+  if (fp64)
+    hipLaunchKernelGGL(k_seg_ghosts<double>, dim3(1), dim3(64), 0, s, p, lo, hi, states,
+                       static_cast<double*>(f0), static_cast<double*>(f1), static_cast<double*>(h0),
+                       static_cast<double*>(h1));
+  else
+    hipLaunchKernelGGL(k_seg_ghosts<float>, dim3(1), dim3(64), 0, s, p, lo, hi, states,
+                       static_cast<float*>(f0), static_cast<float*>(f1), static_cast<float*>(h0),
+                       static_cast<float*>(h1));
+  return hipGetLastError();
+}
 
 hipError_t launch_step(const StepParams& p, bool fp64, int act_mask, bool with_h, bool euler,
                        hipStream_t s) {
@@ -891,7 +1001,7 @@ hipError_t launch_step(const StepParams& p, bool fp64, int act_mask, bool with_h
 }
 
 hipError_t launch_init(const StepParams& p, bool fp64, bool with_h, hipStream_t s) {
-  const unsigned nb = static_cast<unsigned>((p.ncell + kBlock - 1) / kBlock);
+  const unsigned nb = static_cast<unsigned>((p.range + kBlock - 1) / kBlock);
   if (fp64) {
     if (with_h) hipLaunchKernelGGL((k_init<double, true>), dim3(nb), dim3(kBlock), 0, s, p);
     else hipLaunchKernelGGL((k_init<double, false>), dim3(nb), dim3(kBlock), 0, s, p);
@@ -917,7 +1027,7 @@ hipError_t launch_face_slots(const StepParams& p, bool fp64, const double* state
 
 hipError_t launch_moments(const StepParams& p, bool fp64, bool with_h, double* out,
                           unsigned long long* bad, hipStream_t s) {
-  const unsigned nb = static_cast<unsigned>((p.ncell + kBlock - 1) / kBlock);
+  const unsigned nb = static_cast<unsigned>((p.range + kBlock - 1) / kBlock);
   if (fp64) {
     if (with_h) hipLaunchKernelGGL((k_moments<double, true>), dim3(nb), dim3(kBlock), 0, s, p, out, bad);
     else hipLaunchKernelGGL((k_moments<double, false>), dim3(nb), dim3(kBlock), 0, s, p, out, bad);

@@ -232,3 +232,149 @@ def context_for_workload(w, precision=None, stream=None, init=True) -> Context:
     if init:
         ctx.rlb_init_fields(w.eps, w.ux, w.uy, w.uz, w.n if w.with_density else None, w.obstacle)
     return ctx
+
+
+# ---------------------------------------------------------------------------
+# Batched serving (rlb_server_*)
+# ---------------------------------------------------------------------------
+
+EXPORTED += ["rlb_server_create", "rlb_server_submit", "rlb_server_poll", "rlb_server_result",
+             "rlb_server_drain", "rlb_server_stats_get", "rlb_server_destroy",
+             "rlb_request_footprint_bytes"]
+
+
+class rlb_request(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("n", ctypes.c_int32), ("steps", ctypes.c_int64),
+        ("eps", ctypes.POINTER(ctypes.c_double)), ("ux", ctypes.POINTER(ctypes.c_double)),
+        ("uy", ctypes.POINTER(ctypes.c_double)), ("uz", ctypes.POINTER(ctypes.c_double)),
+        ("dens", ctypes.POINTER(ctypes.c_double)),
+        ("eta_over_s", ctypes.c_double), ("tau", ctypes.c_double), ("alpha", ctypes.c_double),
+        ("bc_lo", ctypes.c_int32), ("bc_hi", ctypes.c_int32),
+        ("face_lo", ctypes.c_double * 5), ("face_hi", ctypes.c_double * 5),
+    ]
+
+
+class rlb_server_stats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+        ("failed", ctypes.c_uint64), ("rejected", ctypes.c_uint64), ("capacity_cells", ctypes.c_uint64),
+        ("resident_cells_peak", ctypes.c_uint64), ("resident_requests_peak", ctypes.c_uint64),
+        ("chunks", ctypes.c_uint64), ("global_steps", ctypes.c_uint64),
+        ("cell_updates", ctypes.c_double), ("busy_seconds", ctypes.c_double),
+        ("wall_seconds", ctypes.c_double), ("latency_p50", ctypes.c_double),
+        ("latency_p99", ctypes.c_double), ("latency_max", ctypes.c_double),
+    ]
+
+
+def _load_server(L):
+    if getattr(L, "_server_ready", False):
+        return
+    dp = ctypes.POINTER(ctypes.c_double)
+    vp = ctypes.c_void_p
+    L.rlb_server_create.argtypes = [ctypes.POINTER(rlb_config), ctypes.c_uint64, ctypes.c_int32,
+                                    ctypes.POINTER(vp)]
+    L.rlb_server_submit.argtypes = [vp, ctypes.POINTER(rlb_request), ctypes.POINTER(ctypes.c_uint64)]
+    L.rlb_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]
+    L.rlb_server_result.argtypes = [vp, ctypes.c_uint64, dp, dp, dp, dp, dp, dp,
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    L.rlb_server_drain.argtypes = [vp]
+    L.rlb_server_stats_get.argtypes = [vp, ctypes.POINTER(rlb_server_stats)]
+    L.rlb_server_destroy.argtypes = [vp]
+    L.rlb_server_destroy.restype = None
+    L.rlb_request_footprint_bytes.argtypes = [ctypes.POINTER(rlb_config), ctypes.c_int32]
+    L.rlb_request_footprint_bytes.restype = ctypes.c_uint64
+    for name in ("rlb_server_create", "rlb_server_submit", "rlb_server_poll", "rlb_server_result",
+                 "rlb_server_drain", "rlb_server_stats_get"):
+        getattr(L, name).restype = ctypes.c_int
+    L._server_ready = True
+
+
+def rlb_request_footprint_bytes(common: rlb_config, n: int) -> int:
+    L = load()
+    _load_server(L)
+    return int(L.rlb_request_footprint_bytes(ctypes.byref(common), int(n)))
+
+
+class Server:
+    """Owner of one rlb_server (continuous batching of 1D requests)."""
+
+    def __init__(self, common: rlb_config, budget_bytes: int, chunk_steps: int = 64):
+        self._L = load()
+        _load_server(self._L)
+        self.common = common
+        h = ctypes.c_void_p()
+        _check(self._L.rlb_server_create(ctypes.byref(common), int(budget_bytes), int(chunk_steps),
+                                         ctypes.byref(h)))
+        self._h = h
+        self._sizes = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.rlb_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def rlb_server_submit(self, eps, ux, uy, uz, dens=None, steps=0, eta_over_s=0.0, tau=1.0,
+                          alpha=0.0, bc_lo=RLB_BC_FIXED, bc_hi=RLB_BC_FIXED, face_lo=None,
+                          face_hi=None) -> int:
+        a = [_f64(v) for v in (eps, ux, uy, uz)]
+        d = None if dens is None else _f64(dens)
+        r = rlb_request()
+        r.struct_size = ctypes.sizeof(rlb_request)
+        r.n = a[0].size
+        r.steps = int(steps)
+        r.eps, r.ux, r.uy, r.uz = (_dp(v) for v in a)
+        r.dens = _dp(d)
+        r.eta_over_s, r.tau, r.alpha = float(eta_over_s), float(tau), float(alpha)
+        r.bc_lo, r.bc_hi = int(bc_lo), int(bc_hi)
+        for k in range(5):
+            r.face_lo[k] = float(face_lo[k]) if face_lo is not None else (3.0 if k == 0 else (1.0 if k == 4 else 0.0))
+            r.face_hi[k] = float(face_hi[k]) if face_hi is not None else (3.0 if k == 0 else (1.0 if k == 4 else 0.0))
+        rid = ctypes.c_uint64()
+        _check(self._L.rlb_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
+        self._sizes[rid.value] = r.n
+        return rid.value
+
+    def submit_request(self, q) -> int:
+        """Submit a workloads.ServingRequest."""
+        return self.rlb_server_submit(q.eps, q.ux, q.uy, q.uz, q.dens, q.steps, q.eta_over_s, q.tau,
+                                      q.alpha, q.bc_lo, q.bc_hi, q.face_lo, q.face_hi)
+
+    def rlb_server_poll(self, rid: int) -> bool:
+        d = ctypes.c_int32()
+        _check(self._L.rlb_server_poll(self._h, ctypes.c_uint64(rid), ctypes.byref(d)))
+        return bool(d.value)
+
+    def rlb_server_result(self, rid: int, raise_inadmissible: bool = True):
+        """(fields [eps, ux, uy, uz, n], latency_s, first_bad, guard_events, status)."""
+        n = self._sizes[rid]
+        out = [np.empty(n) for _ in range(5)]
+        lat = ctypes.c_double()
+        bad = ctypes.c_int64()
+        gev = ctypes.c_int64()
+        st = int(self._L.rlb_server_result(self._h, ctypes.c_uint64(rid), *[_dp(o) for o in out],
+                                           ctypes.byref(lat), ctypes.byref(bad), ctypes.byref(gev)))
+        if st != RLB_OK and (st != RLB_E_INADMISSIBLE or raise_inadmissible):
+            _check(st)
+        del self._sizes[rid]
+        return out, lat.value, bad.value, gev.value, st
+
+    def rlb_server_drain(self):
+        _check(self._L.rlb_server_drain(self._h))
+
+    def rlb_server_stats_get(self) -> rlb_server_stats:
+        s = rlb_server_stats()
+        _check(self._L.rlb_server_stats_get(self._h, ctypes.byref(s)))
+        return s

@@ -255,6 +255,73 @@ def random_smooth_state(nx, ny, nz, seed, amp_eps=0.3, umax=0.3, **kw) -> Worklo
     return w
 
 
+@dataclass
+class ServingRequest:
+    """One independent 1D solve of the serving workload."""
+    n: int
+    steps: int
+    eps: np.ndarray
+    ux: np.ndarray
+    uy: np.ndarray
+    uz: np.ndarray
+    dens: np.ndarray
+    eta_over_s: float
+    alpha: float
+    bc_lo: int
+    bc_hi: int
+    face_lo: List[float]
+    face_hi: List[float]
+    tau: float = 1.0
+    arrival: float = 0.0  # seconds after the start of the stream
+
+    def workload(self, precision=MIXED, guard_umax=0.9999, dt=0.25, nu=NU_DEFAULT) -> Workload:
+        """The same solve as a stand-alone Workload (for the oracle and the
+        one-at-a-time path)."""
+        shape = (1, 1, self.n)
+        w = Workload("serving_request", self.n, 1, 1, self.steps, precision=precision,
+                     tau_mode=TAU_ETA_OVER_S, eta_over_s=self.eta_over_s, alpha=self.alpha,
+                     with_density=True, nu=nu, dt=dt,
+                     bc=[self.bc_lo, self.bc_hi] + [BC_PERIODIC] * 4,
+                     face_states=[list(self.face_lo), list(self.face_hi)] + [[3.0, 0, 0, 0, 1.0]] * 4,
+                     guard_umax=guard_umax)
+        w.eps, w.ux, w.uy, w.uz, w.n = (a.reshape(shape).copy() for a in
+                                         (self.eps, self.ux, self.uy, self.uz, self.dens))
+        return w
+
+
+def serving_requests(count=512, nmin=512, nmax=65536, seed=SEED_BASE + 4, steps_factor=2,
+                     ratio_range=(1.5, 20.0), gamma_range=(1.0, 10.0), eta_range=(1e-3, 0.2),
+                     alpha=0.2, rate=None) -> List[ServingRequest]:
+    """Workload 4: independent boosted shock tubes.  Grid sizes log-uniform in
+    [nmin, nmax], temperature ratios log-uniform in ratio_range (eps ratio =
+    ratio^4), a boost with gamma uniform in gamma_range applied to both halves,
+    eta/s log-uniform in eta_range, steps = steps_factor * n, fixed-state ends
+    holding the initial end states.  With `rate` (requests per second) the
+    arrival times follow a Poisson process."""
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    for _ in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+        ratio = math.exp(rng.uniform(math.log(ratio_range[0]), math.log(ratio_range[1])))
+        g0 = rng.uniform(*gamma_range)
+        eos = math.exp(rng.uniform(math.log(eta_range[0]), math.log(eta_range[1])))
+        u0 = math.sqrt(1.0 - 1.0 / (g0 * g0))
+        x = np.arange(n)
+        T = np.where(x < n // 2, ratio, 1.0)
+        eps = 3.0 * T ** 4
+        dens = T ** 3
+        ux = np.full(n, u0)
+        z = np.zeros(n)
+        if rate:
+            t += rng.exponential(1.0 / rate)
+        out.append(ServingRequest(n=n, steps=int(round(steps_factor * n)), eps=eps, ux=ux, uy=z, uz=z.copy(),
+                                  dens=dens, eta_over_s=eos, alpha=alpha, bc_lo=BC_FIXED,
+                                  bc_hi=BC_FIXED, face_lo=[3.0 * ratio ** 4, u0, 0.0, 0.0, ratio ** 3],
+                                  face_hi=[3.0, u0, 0.0, 0.0, 1.0], arrival=t))
+    return out
+
+
 def workload(k: int, **kw) -> Workload:
     """Workload k (1, 2, 3 or 5) at its full size unless overridden."""
     if k == 1:

@@ -37,6 +37,23 @@ def test_struct_layout_matches_header():
     # sizeof(rlb_config) in C: 4 + 3*4 + 4*4 + 5*8 + 6*4 + 30*8 + 2*8, padded to 8
     assert ctypes.sizeof(rlb.rlb_config) == 352
     assert ctypes.sizeof(rlb.rlb_stats) == 64
+    assert ctypes.sizeof(rlb.rlb_request) == 168
+    assert ctypes.sizeof(rlb.rlb_server_stats) == 128
+
+
+def test_struct_sizes_against_the_c_compiler(tmp_path):
+    """Compile a probe of include/rlb.h with gcc and compare the layouts the
+    binding uses."""
+    import subprocess
+    from paper_1302_1125_amd import rlb
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include "rlb.h"\nint main(){printf("%zu %zu %zu %zu",'
+                   ' sizeof(rlb_config), sizeof(rlb_stats), sizeof(rlb_request), sizeof(rlb_server_stats));}')
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert got == [ctypes.sizeof(rlb.rlb_config), ctypes.sizeof(rlb.rlb_stats),
+                   ctypes.sizeof(rlb.rlb_request), ctypes.sizeof(rlb.rlb_server_stats)]
 
 
 def test_host_side_validation_without_device():
