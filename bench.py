@@ -112,6 +112,132 @@ def cpu_baseline(workload: str, precision: int, budget_s: float):
             "kind": "oracle", "sample": f"{sample}, {steps} steps, {total:.1f} s, FP64"}
 
 
+def serving(args):
+    """Batched serving: a Poisson stream of independent boosted 1D shock-tube
+    solves served by one continuously batching server (rlb_server_*),
+    compared with one-at-a-time FP64 solves (rlb_create / rlb_step) of a
+    stratified sample on the same GPU.  Requests that meet an inadmissible
+    state end at the next chunk boundary and are counted as failed; aggregate
+    MLUPS counts the cell-updates actually performed."""
+    import threading
+
+    import numpy as np
+    import torch
+    from paper_1302_1125_amd import rlb, workloads as W
+
+    def log(msg):
+        print(f"[serving] {msg}", file=sys.stderr, flush=True)
+
+    nu = args.serving_nu
+    common = rlb.config_from(8, precision=rlb.RLB_MIXED, tau_mode=rlb.RLB_TAU_ETA_OVER_S,
+                             with_density=True, dt_over_dx=0.25, guard_umax=0.9999, nu=nu)
+    # "stated": gamma0 in [1, 10] applied to both halves, eta/s in [1e-3, 0.2];
+    # "paper": the paper's Riemann regime, tubes at rest, eta/s in [0.01, 0.2]
+    mix = {} if args.serving_mix == "stated" else {"gamma_range": (1.0, 1.0), "eta_range": (0.01, 0.2)}
+    reqs = W.serving_requests(count=args.requests, **mix)
+    lups = [q.n * q.steps for q in reqs]
+    budget = int(args.serving_budget_gib * (1 << 30))
+
+    # capacity: sustained batched rate (cell-updates per busy second) with a
+    # saturating batch of the same distribution, steps capped so that no
+    # single long request sets the duration
+    calib = W.serving_requests(count=max(args.requests // 4, 8), seed=W.SEED_BASE + 40, **mix)
+    for q in calib:
+        q.steps = min(q.steps, 2048)
+    with rlb.Server(common, budget, args.chunk) as srv:
+        ids = [srv.submit_request(q) for q in calib]
+        for i in ids:
+            srv.rlb_server_result(i, raise_inadmissible=False)
+        cst = srv.rlb_server_stats_get()
+    cap_lups = cst.cell_updates / cst.busy_seconds
+    rate = args.load * cap_lups / (sum(lups) / len(lups))
+    rng = np.random.default_rng(W.SEED_BASE + 4)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, len(reqs)))
+    log(f"capacity {cap_lups / 1e6:.0f} MLUPS ({len(calib)} requests, {cst.busy_seconds:.2f} s busy), "
+        f"offered load {args.load} -> {rate:.2f} req/s, {len(reqs)} requests, "
+        f"{sum(lups) / 1e9:.1f} G cell-updates requested")
+
+    ids = [None] * len(reqs)
+    with rlb.Server(common, budget, args.chunk) as srv:
+        start = time.perf_counter()
+
+        def feeder():
+            for k, q in enumerate(reqs):
+                delay = start + arrivals[k] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                ids[k] = srv.submit_request(q)
+                if (k + 1) % 32 == 0:
+                    log(f"submitted {k + 1}/{len(reqs)} at {time.perf_counter() - start:.1f} s")
+
+        th = threading.Thread(target=feeder)
+        th.start()
+        lat, failed, guard, done_lups = [], 0, 0, 0.0
+        for k in range(len(reqs)):
+            while ids[k] is None:
+                time.sleep(0.001)
+            out, l, bad, gev, st = srv.rlb_server_result(ids[k], raise_inadmissible=False)
+            lat.append(l)
+            failed += int(bad >= 0)
+            guard += gev
+            log(f"done {k + 1}/{len(reqs)} n={reqs[k].n} steps={reqs[k].steps} latency {l:.3f} s"
+                + (f" inadmissible at step {bad}" if bad >= 0 else ""))
+        th.join()
+        wall = time.perf_counter() - start
+        sst = srv.rlb_server_stats_get()
+
+    # one-at-a-time FP64 solves (rlb_create / rlb_step of all steps) of a
+    # sample stratified by size give the rate as a function of n; the time
+    # the whole stream would take one at a time is the sum over requests of
+    # n * steps / rate(n), interpolated in log n
+    order = np.argsort([q.n for q in reqs])
+    pick = order[np.linspace(0, len(order) - 1, args.baseline_sample).astype(int)]
+    sample_n, sample_rate = [], []
+    for k in pick:
+        q = reqs[k]
+        w = q.workload(precision=rlb.RLB_FP64, nu=nu)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx = rlb.context_for_workload(w, precision=rlb.RLB_FP64)
+        ctx.status_of_step(q.steps)
+        ctx.rlb_moments()
+        ctx.close()
+        r = q.n * q.steps / (time.perf_counter() - t0)
+        sample_n.append(q.n)
+        sample_rate.append(r)
+        log(f"one-at-a-time FP64 n={q.n} steps={q.steps}: {r / 1e6:.0f} MLUPS")
+    rate_of = lambda n: float(np.interp(np.log(n), np.log(sample_n), sample_rate))
+    base_s = sum(q.n * q.steps / rate_of(q.n) for q in reqs)
+    base = sum(lups) / base_s / 1e6
+    agg = sst.cell_updates / wall / 1e6
+    lat = np.array(lat)
+    out = {
+        "metric": "p50/p99 latency of batched solves & aggregate MLUPS",
+        "value": round(agg, 2), "unit": "MLUPS", "n_gpus": 1, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32-storage/f64-recovery", "data": "synthetic",
+        "config": {"workload": "serving_shock_tubes_1d", "mix": args.serving_mix, "requests": len(reqs),
+                   "nu": nu,
+                   "offered_load": args.load, "rate_per_s": round(rate, 3), "chunk_steps": args.chunk,
+                   "arena_cells": int(sst.capacity_cells),
+                   "cell_updates_requested": float(sum(lups))},
+        "latency_s": {"p50": round(float(np.percentile(lat, 50)), 4),
+                      "p99": round(float(np.percentile(lat, 99)), 4), "max": round(float(lat.max()), 4)},
+        "wall_s": round(wall, 2), "busy_s": round(sst.busy_seconds, 2),
+        "cell_updates_performed": float(sst.cell_updates),
+        "resident_requests_peak": int(sst.resident_requests_peak),
+        "resident_cells_peak": int(sst.resident_cells_peak),
+        "failed_requests": failed, "guard_events": int(guard),
+        "capacity_mlups": round(cap_lups / 1e6, 1),
+        "one_at_a_time_fp64": {"value": round(base, 2), "unit": "MLUPS",
+                               "sample": f"rate(n) from {len(pick)} requests stratified by size (all "
+                                         f"steps), summed over the whole stream",
+                               "est_seconds": round(base_s, 2)},
+        "speedup_vs_one_at_a_time_fp64": round(agg / base, 2),
+        "capacity_speedup_vs_one_at_a_time_fp64": round(cap_lups / 1e6 / base, 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +250,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (counter calibration)")
+    ap.add_argument("--serving", action="store_true", help="batched serving workload instead")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--load", type=float, default=0.8)
+    ap.add_argument("--chunk", type=int, default=64)
+    ap.add_argument("--serving-budget-gib", type=float, default=16.0)
+    ap.add_argument("--serving-nu", type=float, default=4.0)
+    ap.add_argument("--serving-mix", default="stated", choices=["stated", "paper"])
+    ap.add_argument("--baseline-sample", type=int, default=12)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -135,6 +269,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.serving:
+        serving(args)
+        return
     if args.copy_probe_gib > 0:
         # plain copy of known size: rocprofv3 FETCH_SIZE / WRITE_SIZE of this
         # kernel calibrate the counters used for the step kernel's traffic

@@ -212,7 +212,7 @@ typedef struct {
   uint64_t resident_requests_peak;
   uint64_t chunks;                  /* graph launches                          */
   uint64_t global_steps;            /* steps of the batched loop               */
-  double cell_updates;              /* sum of n * steps over completed        */
+  double cell_updates;              /* sum of n * steps taken over retired    */
   double busy_seconds;              /* wall time with resident work            */
   double wall_seconds;              /* first submission to last completion    */
   double latency_p50, latency_p99, latency_max; /* s, submission -> result  */
@@ -237,7 +237,10 @@ rlb_status rlb_server_poll(rlb_server* srv, uint64_t id, int32_t* done);
 /* Block until the request is done, copy its fields (any pointer may be NULL)
    and release it.  latency_s: submission -> result ready on the host;
    first_bad: first inadmissible local step or -1; guard_events: its count.
-   Returns RLB_E_INADMISSIBLE (fields still copied) if a step was inadmissible. */
+   A request that meets an inadmissible state stops at the first chunk
+   boundary after that step (a multiple of chunk_steps from its start, so the
+   same alone and in a mix); its fields are those at that boundary and the
+   call returns RLB_E_INADMISSIBLE. */
 rlb_status rlb_server_result(rlb_server* srv, uint64_t id, double* eps, double* ux, double* uy,
                              double* uz, double* n, double* latency_s, int64_t* first_bad,
                              int64_t* guard_events);

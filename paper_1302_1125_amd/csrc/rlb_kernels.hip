@@ -444,6 +444,16 @@ __device__ __forceinline__ void count_events(unsigned long long* ctr, bool fired
   if (lane == leader) atomicAdd(ctr, static_cast<unsigned long long>(__popcll(mask)));
 }
 
+// Wavefront-aggregated atomicMin of a step index (all lanes of a wave carry
+// the same step): one atomic per wave that met an inadmissible cell.
+__device__ __forceinline__ void flag_bad(unsigned long long* flag, bool bad, long long step) {
+  const unsigned long long mask = __ballot(bad);
+  if (mask == 0ull) return;
+  const int lane = __lane_id();
+  const int leader = __ffsll(static_cast<long long>(mask)) - 1;
+  if (lane == leader) atomicMin(flag, static_cast<unsigned long long>(step));
+}
+
 // Guard (decided in FP64): projected fields of the new moments and blend
 // factors for f and h; true if either factor is below 1.
 template <bool WH>
@@ -649,7 +659,7 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
       count_events(guard_ptr, fired);
     }
     if (!fired) ok = recover<WH>(E, Mx, My, Mz, N0, F);
-    if (!ok) atomicMin(bad_ptr, static_cast<unsigned long long>(step_idx));
+    flag_bad(bad_ptr, !ok, step_idx);
     double K[10];
     feq_coeffs(P, F.eps, F.ux, F.uy, F.uz, F.g2, K);
     T Kt[10];
@@ -676,7 +686,7 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
                      Mz, N0);
     Fields F;
     const bool ok = recover<WH>(E, Mx, My, Mz, N0, F);
-    if (!ok) atomicMin(bad_ptr, static_cast<unsigned long long>(step_idx));
+    flag_bad(bad_ptr, !ok, step_idx);
 
     // 3: the source omega (2 f^eq(t) - f^eq(t - dt)) / (1 + omega) as one
     // coefficient set, computed in FP64 and rounded once to T.
@@ -859,7 +869,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(const StepParams P, double* 
   Fields F;
   const bool ok = recover<WH>(E, Mx, My, Mz, N0, F);
   const bool obst = P.obst != nullptr && P.obst[c] != 0;
-  if (!ok && !obst) atomicMin(bad, 0ull);
+  flag_bad(bad, !ok && !obst, 0);
   out[r] = ok ? F.eps : NAN;
   out[NC + r] = ok ? F.ux : NAN;
   out[2 * NC + r] = ok ? F.uy : NAN;

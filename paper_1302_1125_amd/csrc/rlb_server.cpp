@@ -81,7 +81,8 @@ struct rlb_server {
   long long* h_gstep = nullptr;    // pinned
   unsigned long long* d_bad = nullptr;
   unsigned long long* d_guard = nullptr;
-  unsigned long long* h_counters = nullptr;  // pinned [2 * max_slots]
+  unsigned long long* h_bad = nullptr;       // pinned [max_slots] copy of d_bad
+  unsigned long long* h_guard = nullptr;     // pinned [max_slots] copy of d_guard
   unsigned long long* h_reset = nullptr;     // pinned {kNoBad, 0}
   double* d_face = nullptr;                  // [max_slots][2][5]
   double* h_face = nullptr;                  // pinned [max_slots][2][5]
@@ -152,7 +153,8 @@ void free_server(rlb_server* s) {
   void* dev[] = {s->hist, s->d_segs, s->d_tiles, s->d_gstep, s->d_bad, s->d_guard, s->d_face, s->d_out};
   for (void* p : dev)
     if (p) (void)hipFree(p);
-  void* host[] = {s->h_segs, s->h_tiles, s->h_gstep, s->h_counters, s->h_reset, s->h_face, s->h_out};
+  void* host[] = {s->h_segs, s->h_tiles, s->h_gstep, s->h_guard, s->h_bad, s->h_reset, s->h_face,
+                  s->h_out};
   for (void* p : host)
     if (p) (void)hipHostFree(p);
   if (s->ev) (void)hipEventDestroy(s->ev);
@@ -311,49 +313,66 @@ hipError_t upload_tables(rlb_server* s) {
   return e;
 }
 
-// Retire requests whose steps are done after the chunk that ended at s->gstep.
+// Retire requests whose steps are done after the chunk that ended at
+// s->gstep, and requests that met an inadmissible state (they end at the
+// first chunk boundary after it).  s->h_bad holds the per-slot flags copied
+// after the chunk.  The moments of all retiring requests are computed and
+// copied back under one synchronisation.
 hipError_t retire(rlb_server* s) {
   std::vector<uint64_t> done;
-  for (uint64_t id : s->active)
-    if (s->gstep - s->reqs[id].start >= s->reqs[id].steps) done.push_back(id);
+  long long total = 0;
+  for (uint64_t id : s->active) {
+    const Req& r = s->reqs[id];
+    if (s->gstep - r.start >= r.steps || s->h_bad[r.slot] != kNoBad) {
+      done.push_back(id);
+      total += r.n;
+    }
+  }
   if (done.empty()) return hipSuccess;
   hipError_t e = hipSuccess;
+  if (s->out_cells < total) {
+    if (s->d_out) (void)hipFree(s->d_out);
+    if (s->h_out) (void)hipHostFree(s->h_out);
+    s->d_out = nullptr;
+    s->h_out = nullptr;
+    s->out_cells = std::max<long long>(total, 1 << 16);
+    e = dmalloc(&s->d_out, 5 * sizeof(double) * s->out_cells);
+    if (e == hipSuccess) e = hmalloc(&s->h_out, 5 * sizeof(double) * s->out_cells);
+    if (e != hipSuccess) return e;
+  }
+  long long off = 0;
   for (uint64_t id : done) {
-    Req& r = s->reqs[id];
-    if (s->out_cells < r.n) {
-      if (s->d_out) (void)hipFree(s->d_out);
-      if (s->h_out) (void)hipHostFree(s->h_out);
-      s->d_out = nullptr;
-      s->h_out = nullptr;
-      s->out_cells = std::max<long long>(r.n, 1 << 16);
-      e = dmalloc(&s->d_out, 5 * sizeof(double) * s->out_cells);
-      if (e == hipSuccess) e = hmalloc(&s->h_out, 5 * sizeof(double) * s->out_cells);
-      if (e != hipSuccess) return e;
-    }
+    const Req& r = s->reqs[id];
     rlb::StepParams p = s->base;
     p.f_in = s->f[0];  // chunks are even, so the current copy is 0
     p.h_in = s->h[0];
     p.cell0 = r.base + 1;
     p.range = r.n;
-    e = rlb::launch_moments(p, s->fp64, s->with_h, s->d_out, s->d_bad + s->max_slots, s->stream);
+    e = rlb::launch_moments(p, s->fp64, s->with_h, s->d_out + 5 * off, s->d_bad + s->max_slots,
+                            s->stream);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(s->h_out, s->d_out, 5 * sizeof(double) * r.n, hipMemcpyDeviceToHost, s->stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(s->h_counters, s->d_bad + r.slot, sizeof(unsigned long long),
+      e = hipMemcpyAsync(s->h_guard + r.slot, s->d_guard + r.slot, sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, s->stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(s->h_counters + 1, s->d_guard + r.slot, sizeof(unsigned long long),
-                         hipMemcpyDeviceToHost, s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return e;
-    std::memcpy(r.io.data(), s->h_out, 5 * sizeof(double) * r.n);
-    r.first_bad = s->h_counters[0] == kNoBad ? -1 : static_cast<long long>(s->h_counters[0]);
-    r.guard = s->h_counters[1];
+    off += r.n;
+  }
+  e = hipMemcpyAsync(s->h_out, s->d_out, 5 * sizeof(double) * total, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return e;
+  off = 0;
+  for (uint64_t id : done) {
+    Req& r = s->reqs[id];
+    std::memcpy(r.io.data(), s->h_out + 5 * off, 5 * sizeof(double) * r.n);
+    off += r.n;
+    const unsigned long long bad = s->h_bad[r.slot];
+    r.first_bad = bad == kNoBad ? -1 : static_cast<long long>(bad);
+    r.guard = s->h_guard[r.slot];
     r.done_at = Clock::now();
     r.state = r.first_bad >= 0 ? kFailed : kDone;
     s->n_done += 1;
     if (r.first_bad >= 0) s->n_fail += 1;
-    s->cell_updates += static_cast<double>(r.n) * static_cast<double>(r.steps);
+    const long long ran = std::min<long long>(r.steps, s->gstep - r.start);
+    s->cell_updates += static_cast<double>(r.n) * static_cast<double>(ran);
     s->latencies.push_back(std::chrono::duration<double>(r.done_at - r.arrival).count());
     s->last_done = r.done_at;
     arena_free(s, r.base, r.cells);
@@ -392,6 +411,9 @@ void worker_loop(rlb_server* s) {
     }
     const auto t0 = Clock::now();
     if (e == hipSuccess) e = hipGraphLaunch(g, s->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->h_bad, s->d_bad, sizeof(unsigned long long) * s->max_slots,
+                         hipMemcpyDeviceToHost, s->stream);
     // let callers submit while the chunk runs
     lk.unlock();
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -518,7 +540,8 @@ rlb_status rlb_server_create(const rlb_config* common, uint64_t budget_bytes, in
   if (e == hipSuccess) e = hmalloc(&s->h_gstep, sizeof(long long));
   if (e == hipSuccess) e = dmalloc(&s->d_bad, sizeof(unsigned long long) * (s->max_slots + 1));
   if (e == hipSuccess) e = dmalloc(&s->d_guard, sizeof(unsigned long long) * s->max_slots);
-  if (e == hipSuccess) e = hmalloc(&s->h_counters, sizeof(unsigned long long) * 2);
+  if (e == hipSuccess) e = hmalloc(&s->h_guard, sizeof(unsigned long long) * s->max_slots);
+  if (e == hipSuccess) e = hmalloc(&s->h_bad, sizeof(unsigned long long) * s->max_slots);
   if (e == hipSuccess) e = hmalloc(&s->h_reset, sizeof(unsigned long long) * 2);
   if (e == hipSuccess) e = dmalloc(&s->d_face, sizeof(double) * 10 * s->max_slots);
   if (e == hipSuccess) e = hmalloc(&s->h_face, sizeof(double) * 10 * s->max_slots);
