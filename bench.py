@@ -79,6 +79,59 @@ def traffic_entry(workload: str, precision: str):
     return e.get("bytes_per_launch")
 
 
+def _counter_means(csv_path: str, counter: str):
+    """Mean per-dispatch value of a rocprofv3 counter (CSV output), by kernel name."""
+    import csv
+    acc = {}
+    with open(csv_path, newline="") as f:
+        for row in csv.DictReader(f):
+            if row["Counter_Name"] != counter:
+                continue
+            acc.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def record_traffic(args):
+    """Turn four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE of the step
+    kernel under this bench, and of the plain-copy probe) into bytes per
+    launch of the step kernel, scaled by what each counter reads for the copy
+    of known size; written to the traffic file with the kernel source hash."""
+    fetch_csv, write_csv, cfetch_csv, cwrite_csv = args.record_traffic
+    copy_bytes = int(args.copy_probe_gib * (1 << 30)) // 4 * 4
+
+    def step_kib(path, counter):
+        m = {k: v for k, v in _counter_means(path, counter).items() if "k_step" in k}
+        if len(m) != 1:
+            raise SystemExit(f"expected one k_step kernel in {path}, found {list(m)}")
+        return next(iter(m.values()))
+
+    def copy_kib(path, counter):
+        m = {k: v for k, v in _counter_means(path, counter).items() if "MulFunctor" in k or "mul" in k.lower()}
+        if not m:
+            raise SystemExit(f"no multiply kernel in {path}")
+        return max(m.values())
+
+    f_scale = copy_bytes / (copy_kib(cfetch_csv, "FETCH_SIZE") * 1024)
+    w_scale = copy_bytes / (copy_kib(cwrite_csv, "WRITE_SIZE") * 1024)
+    fetch = step_kib(fetch_csv, "FETCH_SIZE") * 1024 * f_scale
+    write = step_kib(write_csv, "WRITE_SIZE") * 1024 * w_scale
+    try:
+        with open(TRAFFIC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        d = {}
+    d[f"{args.workload}:{args.precision}"] = {
+        "kernel_hash": kernel_hash(), "bytes_per_launch": round(fetch + write),
+        "fetch_bytes": round(fetch), "write_bytes": round(write),
+        "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+        "copy_probe_bytes": copy_bytes}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+        f.write("\n")
+    print(json.dumps(d[f"{args.workload}:{args.precision}"]))
+
+
 def cpu_baseline(workload: str, precision: int, budget_s: float):
     """FP64 CPU oracle on a bounded sample of the same workload recipe."""
     from oracle import oracle as O
@@ -250,6 +303,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (counter calibration)")
+    ap.add_argument("--record-traffic", nargs=4, metavar=("STEP_FETCH", "STEP_WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="rocprofv3 counter CSVs -> traffic file (no GPU needed); with --copy-probe-gib")
     ap.add_argument("--serving", action="store_true", help="batched serving workload instead")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--load", type=float, default=0.8)
@@ -263,6 +318,12 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(domain decomposition is described in DESIGN.md, not implemented).", file=sys.stderr)
         sys.exit(2)
+
+    if args.record_traffic:
+        if args.copy_probe_gib <= 0:
+            raise SystemExit("--record-traffic needs --copy-probe-gib (the size the copy probe ran with)")
+        record_traffic(args)
+        return
 
     import torch
     from paper_1302_1125_amd import rlb
