@@ -63,7 +63,8 @@ enum { RLB_BC_PERIODIC = 0, RLB_BC_FIXED = 1, RLB_BC_OUTFLOW = 2 };
 typedef struct {
   uint32_t struct_size; /* = sizeof(rlb_config) (ABI check)                 */
   int32_t nx, ny, nz;   /* grid; ny == 1 requires nz == 1; nx >= 2.  Axes
-                           of size 1 must be periodic (quasi-1D / 2D).      */
+                           of size 1 must be periodic (quasi-1D / 2D).
+                           At most 2^28 - 128 cells in all.                 */
   int32_t precision;    /* RLB_FP64: populations stored and updated in FP64.
                            RLB_MIXED: populations stored and streamed in
                            FP32; moments accumulated in FP64; recovery and
@@ -221,7 +222,8 @@ typedef struct {
 /* Create a server.  From *common only precision, collision, tau_mode,
    with_density, nu, dt_over_dx and the guard fields are used (grid, bc, tau,
    eta_over_s and alpha are per request).  budget_bytes: device memory of the
-   arena (populations, ping-pong, previous fields); chunk_steps: steps per
+   arena (populations, ping-pong, previous fields; at most 2^28 - 128 cells
+   are used); chunk_steps: steps per
    graph launch, even, >= 2.  The server runs on a stream it creates. */
 rlb_status rlb_server_create(const rlb_config* common, uint64_t budget_bytes, int32_t chunk_steps,
                              rlb_server** out);

@@ -69,7 +69,7 @@ rlb_status validate(const rlb_config* c) {
   if (c->nx < 2 || c->ny < 1 || c->nz < 1) return fail(RLB_E_INVALID_ARG, "grid: nx >= 2, ny, nz >= 1");
   if (c->ny == 1 && c->nz != 1) return fail(RLB_E_INVALID_ARG, "ny == 1 requires nz == 1");
   const long long nc = static_cast<long long>(c->nx) * c->ny * c->nz;
-  if (nc > (1ll << 31) - 64) return fail(RLB_E_INVALID_ARG, "grid too large (at most 2^31 - 64 cells)");
+  if (nc > rlb::kMaxCells) return fail(RLB_E_INVALID_ARG, "grid too large (at most 2^28 - 128 cells)");
   if (c->precision != RLB_FP64 && c->precision != RLB_MIXED) return fail(RLB_E_INVALID_ARG, "precision");
   if (c->collision != RLB_COLL_IMPLICIT && c->collision != RLB_COLL_EULER)
     return fail(RLB_E_INVALID_ARG, "collision");

@@ -24,6 +24,12 @@ inline long long population_stride(long long ncell) {
   return (ncell + kFaceSlots + 63) / 64 * 64;
 }
 
+// Largest grid (or serving arena) in cells.  Kernels address every array by
+// 32-bit byte offsets from a per-array base; with FP64 arrays (populations in
+// FP64 mode, previous-step fields always) 8 * population_stride must stay
+// below 2^31.  The serving arena obeys the same limit.
+constexpr long long kMaxCells = (1ll << 28) - 128;
+
 // Everything a step kernel needs, passed by value (kernarg segment).
 struct StepParams {
   const void* f_in;

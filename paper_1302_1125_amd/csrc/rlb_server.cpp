@@ -504,8 +504,7 @@ rlb_status rlb_server_create(const rlb_config* common, uint64_t budget_bytes, in
     return rlb_set_error(RLB_E_INVALID_ARG, "chunk_steps must be even, 2..4096");
   const uint64_t bpc = bytes_per_cell(c);
   long long cap = static_cast<long long>(budget_bytes / bpc) / kAlign * kAlign;
-  const long long max_cap = (static_cast<long long>(1) << 31) / static_cast<long long>(c.precision == RLB_FP64 ? 8 : 4) - 1024;
-  cap = std::min(cap, max_cap);
+  cap = std::min(cap, rlb::kMaxCells / kAlign * kAlign);
   if (cap < kAlign * 2) return rlb_set_error(RLB_E_INVALID_ARG, "budget too small");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {

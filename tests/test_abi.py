@@ -72,3 +72,20 @@ def test_host_side_validation_without_device():
     assert n * (4 * 19 * 4 + 5 * 8) <= fp <= n * (4 * 19 * 4 + 5 * 8) * 1.01 + 4096
     bad = rlb.config_from(8, 1, 4)
     assert rlb.rlb_footprint_bytes(bad) == 0
+
+
+def test_grid_limit_keeps_byte_offsets_in_range():
+    """Kernels address arrays by 32-bit byte offsets: a grid whose FP64 arrays
+    would reach 2^31 bytes is rejected before any allocation."""
+    from paper_1302_1125_amd import rlb
+    if not os.path.exists(rlb.LIB_PATH):
+        pytest.skip("librlb.so not built")
+    rlb.load()
+    limit = (1 << 28) - 128
+    ok = rlb.config_from(limit, 1, 1, precision=rlb.RLB_MIXED, with_density=False)
+    assert rlb.rlb_footprint_bytes(ok) > 0
+    for prec in (rlb.RLB_MIXED, rlb.RLB_FP64):
+        big = rlb.config_from(limit + 1, 1, 1, precision=prec, with_density=False)
+        assert rlb.rlb_footprint_bytes(big) == 0
+        big3 = rlb.config_from(1024, 1024, 257, precision=prec)
+        assert rlb.rlb_footprint_bytes(big3) == 0
