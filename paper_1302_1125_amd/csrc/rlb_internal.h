@@ -20,8 +20,11 @@ constexpr int kBcPeriodic = 0, kBcFixed = 1, kBcOutflow = 2;
 // (written once at creation in both ping-pong copies).  A neighbour index
 // that crosses a FIXED face points at the face slot, so boundary conditions
 // are pure index mapping inside the step kernel.
+// Elements per population array: the ncell cells, the kFaceSlots face slots,
+// one trash slot (index ncell + kFaceSlots: lanes whose results are discarded
+// store there), padded to a multiple of 64.
 inline long long population_stride(long long ncell) {
-  return (ncell + kFaceSlots + 63) / 64 * 64;
+  return (ncell + kFaceSlots + 1 + 63) / 64 * 64;
 }
 
 // Largest grid (or serving arena) in cells.  Kernels address every array by

@@ -252,7 +252,9 @@ __device__ __forceinline__ T dflux_neg(T m1, T c0, T p1, T p2) {
 // uniform across the wavefront (scalar base, 32-bit vector offset).
 template <int ACT>
 struct Nbr {
-  unsigned c;
+  unsigned c;        // byte offset of the value this lane loads (its cell)
+  unsigned cs;       // byte offset its results are stored at (c, or the trash slot)
+  unsigned hr, hx;   // staged tiles: halo row / halo column position this lane loads
   unsigned o[3][4];
 };
 
@@ -281,6 +283,7 @@ __device__ __forceinline__ void make_nbr(const StepParams& P, int x, int y, int 
       N.o[a][j] = static_cast<unsigned>(idx) * static_cast<unsigned>(sizeof(T));
     }
   }
+  N.cs = N.c;
 }
 
 // Neighbour byte offsets of interior cell `local` of a batched 1D segment
@@ -289,6 +292,7 @@ template <typename T>
 __device__ __forceinline__ void make_seg_nbr(const SegDesc& sd, int local, Nbr<1>& N) {
   const long long c = sd.base + 1 + local;
   N.c = static_cast<unsigned>(c) * static_cast<unsigned>(sizeof(T));
+  N.cs = N.c;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int k = j < 2 ? j - 2 : j - 1;
@@ -333,6 +337,134 @@ __device__ __forceinline__ T ldb_nt(const T* __restrict__ base, unsigned off) {
   else return *p;
 }
 
+// ---------------------------------------------------------------------------
+// Staged tiles (2D and 3D).  A workgroup updates a tile of kTY rows of 64
+// cells (one row per wavefront).  The x and y neighbours of its cells are not
+// loaded one by one: per population array, each wavefront writes its own row
+// of centre values into an LDS tile of (kTY + 4) x 68 values (rows y0 - 2 ..
+// y0 + kTY + 1, columns x0 - 2 .. x0 + 65), loads one halo row (y0 - 2,
+// y0 - 1, y0 + kTY, y0 + kTY + 1 for wavefronts 0..3) and the four halo
+// cells of its row (lanes 0..3), and after a barrier every x and y
+// neighbour is an LDS read.  z neighbours stay global loads.  The arrays go
+// through LDS in stages of a few populations (f and h together).  Lanes of
+// a ragged tile past the x or y end hold the boundary-mapped value of their
+// position, so that every value the tile reads is right; they update
+// nothing (stores go to the trash slot of each array).
+// ---------------------------------------------------------------------------
+constexpr int kTY = kBlock / 64;   // rows per tile
+constexpr int kLW = 64 + 4;        // LDS row: x0 - 2 .. x0 + 65
+constexpr int kLH = kTY + 4;       // LDS rows: y0 - 2 .. y0 + kTY + 1
+
+template <typename T, bool WH>
+struct Stages {
+  static constexpr int n = (WH && sizeof(T) == 8) ? 4 : 2;   // stages per step
+  static constexpr int pops = (Q + n - 1) / n;               // populations per stage
+  static constexpr int arrays = (WH ? 2 : 1) * pops;         // LDS arrays per stage
+};
+
+// Cell index (or face slot) of position (px, py) of plane z for px in
+// [-2, nx + 1], py in [-2, ny + 1], with the x and y boundary conditions.
+__device__ __forceinline__ long long map_xy(const StepParams& P, int px, int py, int z) {
+  const int nx = P.nx, ny = P.ny;
+  if (py < 0 || py >= ny) {
+    const int side = py < 0 ? 0 : 1;
+    const int b = P.bc[2 + side];
+    if (b == kBcFixed) return P.ncell + 2 + side;
+    py = b == kBcPeriodic ? (py < 0 ? py + ny : py - ny) : (py < 0 ? 0 : ny - 1);
+  }
+  if (px < 0 || px >= nx) {
+    const int side = px < 0 ? 0 : 1;
+    const int b = P.bc[side];
+    if (b == kBcFixed) return P.ncell + side;
+    px = b == kBcPeriodic ? (px < 0 ? px + nx : px - nx) : (px < 0 ? 0 : nx - 1);
+  }
+  return static_cast<long long>(nx) * (py + static_cast<long long>(ny) * z) + px;
+}
+
+// Offsets of a staged tile's lane at (x, y, z) (x, y possibly past the end):
+// its value, z neighbours, halo row and halo column positions.
+template <typename T, int ACT>
+__device__ __forceinline__ void make_nbr_stg(const StepParams& P, int x, int y, int z, bool inside,
+                                             Nbr<ACT>& N) {
+  const int lane = static_cast<int>(__lane_id());
+  const int w = static_cast<int>(threadIdx.x) >> 6;
+  const int px = x < P.nx + 1 ? x : P.nx + 1;
+  const int py = y < P.ny + 1 ? y : P.ny + 1;
+  const unsigned sz = static_cast<unsigned>(sizeof(T));
+  const long long c = map_xy(P, px, py, z);
+  N.c = static_cast<unsigned>(c) * sz;
+  N.cs = N.c;
+  const int y0 = y - w, x0 = x - lane;
+  int hy = y0 - 2 + (w < 2 ? w : kTY + w);
+  hy = hy < P.ny + 1 ? hy : P.ny + 1;
+  N.hr = static_cast<unsigned>(map_xy(P, px, hy, z)) * sz;
+  int hxp = lane < 2 ? x0 - 2 + lane : x0 + 62 + lane;
+  hxp = hxp < P.nx + 1 ? hxp : P.nx + 1;
+  N.hx = lane < 4 ? static_cast<unsigned>(map_xy(P, hxp, py, z)) * sz : N.c;
+  if constexpr (axis_on<ACT>(2)) {
+    const long long st = static_cast<long long>(P.nx) * P.ny;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = j < 2 ? j - 2 : j - 1;
+      const int q = z + k;
+      long long idx = c + k * st;
+      if (q < 0 || q >= P.nz) {
+        const int side = q < 0 ? 0 : 1;
+        const int b = P.bc[4 + side];
+        if (b == kBcFixed) idx = P.ncell + 4 + side;
+        else if (b == kBcPeriodic) idx = c + (q < 0 ? k + P.nz : k - P.nz) * st;
+        else idx = c + ((q < 0 ? 0 : P.nz - 1) - z) * st;
+      }
+      // a lane past the x or y end needs no z neighbours: read its own value
+      N.o[2][j] = inside ? static_cast<unsigned>(idx) * sz : N.c;
+    }
+  }
+}
+
+// Fill the LDS tiles of populations [S0, S1) (f in slots 0.., h after them):
+// halo loads first, then (after `sync_before`: the previous stage's reads are
+// done) the centre row, halo row and halo columns, then a barrier.
+template <typename T, int ACT, bool WH, int S0, int S1>
+__device__ __forceinline__ void stage_fill(T (*L)[kLH][kLW], const T* __restrict__ fin,
+                                           const T* __restrict__ hin, long long S,
+                                           const Nbr<ACT>& N, const T* fc, const T* hc,
+                                           bool sync_before) {
+  constexpr int NP = S1 - S0;
+  const int lane = static_cast<int>(__lane_id());
+  const int w = static_cast<int>(threadIdx.x) >> 6;
+  T vr[NP], vrh[NP], vx[NP], vxh[NP];
+  static_for<0, NP>([&](auto k) {
+    constexpr int I = S0 + k;
+    vr[k] = ldb(fin + I * S, N.hr);
+    if constexpr (WH && vcomp(I, 1) != 0) vrh[k] = ldb(hin + I * S, N.hr);
+  });
+  if (lane < 4) {
+    static_for<0, NP>([&](auto k) {
+      constexpr int I = S0 + k;
+      vx[k] = ldb(fin + I * S, N.hx);
+      if constexpr (WH && vcomp(I, 0) != 0) vxh[k] = ldb(hin + I * S, N.hx);
+    });
+  }
+  if (sync_before) __syncthreads();
+  const int hrow = w < 2 ? w : kTY + w;
+  const int hcol = lane < 2 ? lane : 64 + lane;
+  static_for<0, NP>([&](auto k) {
+    constexpr int I = S0 + k;
+    L[k][2 + w][2 + lane] = fc[I];
+    L[k][hrow][2 + lane] = vr[k];
+    if constexpr (WH && (vcomp(I, 0) != 0 || vcomp(I, 1) != 0)) L[NP + k][2 + w][2 + lane] = hc[I];
+    if constexpr (WH && vcomp(I, 1) != 0) L[NP + k][hrow][2 + lane] = vrh[k];
+  });
+  if (lane < 4) {
+    static_for<0, NP>([&](auto k) {
+      constexpr int I = S0 + k;
+      L[k][2 + w][hcol] = vx[k];
+      if constexpr (WH && vcomp(I, 0) != 0) L[NP + k][2 + w][hcol] = vxh[k];
+    });
+  }
+  __syncthreads();
+}
+
 // Star stencil of one population: per active axis the values the limited
 // flux (and, with LAP, the Laplacian) needs: e^a > 0: x-2, x-1, x+1;
 // e^a < 0: x-1, x+1, x+2; e^a = 0 with LAP: x-1, x+1.
@@ -358,6 +490,55 @@ __device__ __forceinline__ void gather(const T* __restrict__ arr, const Nbr<ACT>
     } else if (LAP) {
       s.v[a][0] = ldb(arr, N.o[a][1]);
       s.v[a][1] = ldb(arr, N.o[a][2]);
+    }
+  }
+}
+
+// Stencil of population I of a staged tile: x and y from the LDS tile L
+// (this lane at row 2 + wavefront, column 2 + lane), z from the array.
+template <typename T, int ACT, int I, bool LAP>
+__device__ __forceinline__ void gather_lds(const T (*L)[kLW], const T* __restrict__ arr,
+                                           const Nbr<ACT>& N, Sten<T>& s) {
+  const int r = 2 + (static_cast<int>(threadIdx.x) >> 6);
+  const int c = 2 + static_cast<int>(__lane_id());
+  constexpr int ex = vcomp(I, 0), ey = vcomp(I, 1);
+  if constexpr (ex > 0) {
+    s.v[0][0] = L[r][c - 2];
+    s.v[0][1] = L[r][c - 1];
+    s.v[0][2] = L[r][c + 1];
+  } else if constexpr (ex < 0) {
+    s.v[0][0] = L[r][c - 1];
+    s.v[0][1] = L[r][c + 1];
+    s.v[0][2] = L[r][c + 2];
+  } else if constexpr (LAP) {
+    s.v[0][0] = L[r][c - 1];
+    s.v[0][1] = L[r][c + 1];
+  }
+  if constexpr (ey > 0) {
+    s.v[1][0] = L[r - 2][c];
+    s.v[1][1] = L[r - 1][c];
+    s.v[1][2] = L[r + 1][c];
+  } else if constexpr (ey < 0) {
+    s.v[1][0] = L[r - 1][c];
+    s.v[1][1] = L[r + 1][c];
+    s.v[1][2] = L[r + 2][c];
+  } else if constexpr (LAP) {
+    s.v[1][0] = L[r - 1][c];
+    s.v[1][1] = L[r + 1][c];
+  }
+  if constexpr (axis_on<ACT>(2)) {
+    constexpr int ez = vcomp(I, 2);
+    if constexpr (ez > 0) {
+      s.v[2][0] = ldb(arr, N.o[2][0]);
+      s.v[2][1] = ldb(arr, N.o[2][1]);
+      s.v[2][2] = ldb(arr, N.o[2][2]);
+    } else if constexpr (ez < 0) {
+      s.v[2][0] = ldb(arr, N.o[2][1]);
+      s.v[2][1] = ldb(arr, N.o[2][2]);
+      s.v[2][2] = ldb(arr, N.o[2][3]);
+    } else if constexpr (LAP) {
+      s.v[2][0] = ldb(arr, N.o[2][1]);
+      s.v[2][1] = ldb(arr, N.o[2][2]);
     }
   }
 }
@@ -400,7 +581,8 @@ __device__ __forceinline__ void stream_terms(const Sten<T>& s, T c0, T dtv, T& d
   if (first_n) nsum = T(0);
 }
 
-// Cell of this thread (see StepParams::order); false if outside the grid.
+// Cell of this thread (see StepParams::order); false if the workgroup's tile
+// is outside the grid (x and y of a ragged tile may lie past the end).
 __device__ __forceinline__ bool cell_of(const StepParams& P, int& x, int& y, int& z) {
   const unsigned b = blockIdx.x;
   const long long l = b / kXcds;
@@ -432,7 +614,7 @@ __device__ __forceinline__ bool cell_of(const StepParams& P, int& x, int& y, int
   }
   x = tx * P.tile_x + static_cast<int>(threadIdx.x) % P.tile_x;
   y = ty * P.tile_y + static_cast<int>(threadIdx.x) / P.tile_x;
-  return x < P.nx && y < P.ny;
+  return true;
 }
 
 // Wavefront-aggregated counter increment.
@@ -546,6 +728,7 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
     const StepParams P) {
   const long long S = P.pstride;
   Nbr<ACT> N;
+  bool inside = true;  // the lane holds a cell of the grid
   // run parameters (per request in segment mode)
   double kappa_d = P.kappa, nu2e = P.nu2_etas, tau_u = P.tau;
   unsigned long long* bad_ptr = P.bad_step;
@@ -577,10 +760,22 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
   } else {
     int x, y, z;
     if (!cell_of(P, x, y, z)) return;
-    make_nbr<T, ACT>(P, x, y, z, N);
+    if constexpr (ACT == 1) {
+      if (x >= P.nx) return;
+      make_nbr<T, ACT>(P, x, y, z, N);
+    } else {
+      // staged tile: every lane stays for the barriers (see make_nbr_stg)
+      inside = x < P.nx && y < P.ny;
+      make_nbr_stg<T, ACT>(P, x, y, z, inside, N);
+    }
   }
-  const unsigned cb = N.c;                                  // byte offset of the cell
-  const unsigned cd = (cb / sizeof(T)) * 8u;                // byte offset in FP64 arrays
+  const unsigned trash = static_cast<unsigned>(P.ncell + kFaceSlots) * static_cast<unsigned>(sizeof(T));
+  if (!inside) N.cs = trash;
+  bool real = inside;                                       // this lane updates its cell
+  const unsigned cl = N.c;                                  // byte offset loaded from
+  const unsigned cb = N.cs;                                 // byte offset stored to
+  const unsigned cd = (cl / sizeof(T)) * 8u;                // byte offset in FP64 arrays
+  const unsigned cdl = inside ? cd : 0u;                    // previous fields read (any cell if outside)
   const long long NC = P.ncell;
   const double* __restrict__ h0 = hist;
   const double* __restrict__ h1 = hist + NC;
@@ -588,29 +783,34 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
   const double* __restrict__ h3 = hist + 3 * NC;
   const double* __restrict__ h4 = hist + 4 * NC;
 
-  // Obstacle cells: held at the equilibrium of their prescribed fields.
-  if (!SEG && obst != nullptr && obst[cb / sizeof(T)] != 0) {
+  // Obstacle cells: held at the equilibrium of their prescribed fields.  In a
+  // staged tile the lane stays (its value is a neighbour) and updates nothing.
+  if (!SEG && obst != nullptr && inside && obst[cl / sizeof(T)] != 0) {
     const double eps = ldb(h0, cd), ux = ldb(h1, cd), uy = ldb(h2, cd), uz = ldb(h3, cd),
                  nn = ldb(h4, cd);
     const double g2 = 1.0 / (1.0 - (ux * ux + uy * uy + uz * uz));
     double K[10];
     feq_coeffs(P, eps, ux, uy, uz, g2, K);
-    static_for<0, Q>([&](auto I) { stb(fout + I * S, cb, static_cast<T>(weight(I) * bracket<I>(K))); });
+    static_for<0, Q>([&](auto I) { stb(fout + I * S, cl, static_cast<T>(weight(I) * bracket<I>(K))); });
     if constexpr (WH) {
       double H[10];
       heq_coeffs(P, nn, ux, uy, uz, sqrt(g2), H);
       static_for<0, Q>(
-          [&](auto I) { stb(hout + I * S, cb, static_cast<T>(wprime<I>(P) * bracket<I>(H))); });
+          [&](auto I) { stb(hout + I * S, cl, static_cast<T>(wprime<I>(P) * bracket<I>(H))); });
     }
-    return;
+    if constexpr (ACT == 1) return;
+    real = false;
   }
+  const unsigned cbs = real ? cb : trash;  // obstacle lanes of a staged tile store to the trash slot
 
   T fc[Q];
   T hc[Q];
   static_for<0, Q>([&](auto I) {
-    fc[I] = ldb(fin + I * S, cb);
-    if constexpr (WH) hc[I] = ldb(hin + I * S, cb);
+    fc[I] = ldb(fin + I * S, cl);
+    if constexpr (WH) hc[I] = ldb(hin + I * S, cl);
   });
+  // LDS tiles of a stage (2D/3D)
+  __shared__ T lds[ACT != 1 ? Stages<T, WH>::arrays : 1][kLH][kLW];
 
   const T dtv = static_cast<T>(P.dtv);
   constexpr T NA2 = T(2 * n_axes<ACT>());
@@ -619,33 +819,55 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
   constexpr int kBatch = Batch<ACT>::value;
   constexpr int kNumBatches = Batch<ACT>::count;
 
+  // Streaming phase: per_pop(I, stencil of f_I, stencil of h_I) for every
+  // population, stencils from the staged LDS tiles (2D/3D, stage by stage) or
+  // from the arrays (1D, in batches).
+  auto stream_all = [&](auto&& per_pop) {
+    if constexpr (ACT != 1) {
+      constexpr int NS = Stages<T, WH>::n, PP = Stages<T, WH>::pops;
+      static_for<0, NS>([&](auto st) {
+        constexpr int S0 = st * PP;
+        constexpr int S1 = S0 + PP < Q ? S0 + PP : Q;
+        stage_fill<T, ACT, WH, S0, S1>(lds, fin, hin, S, N, fc, hc, st > 0);
+        static_for<S0, S1>([&](auto I) {
+          Sten<T> sf, sh;
+          gather_lds<T, ACT, I, (I != 0)>(lds[I - S0], fin + I * S, N, sf);
+          if constexpr (WH) gather_lds<T, ACT, I, false>(lds[(S1 - S0) + (I - S0)], hin + I * S, N, sh);
+          per_pop(I, sf, sh);
+        });
+      });
+    } else {
+      static_for<0, kNumBatches>([&](auto g) {
+        Sten<T> sf[kBatch], sh[kBatch];
+        static_for<0, kBatch>([&](auto k) {
+          constexpr int I = g * kBatch + k;
+          if constexpr (I < Q) {
+            gather<T, ACT, I, (I != 0)>(fin + I * S, N, sf[k]);
+            if constexpr (WH) gather<T, ACT, I, false>(hin + I * S, N, sh[k]);
+          }
+        });
+        static_for<0, kBatch>([&](auto k) {
+          constexpr int I = g * kBatch + k;
+          if constexpr (I < Q) per_pop(std::integral_constant<int, I>{}, sf[k], sh[k]);
+        });
+      });
+    }
+  };
+
   if constexpr (EULER) {
     // Streaming and bulk term without collision, then f := f^eq of the
     // post-streaming moments (Sec. III, inviscid case).
     const T kap = static_cast<T>(kappa_d);
-    static_for<0, kNumBatches>([&](auto g) {
-      Sten<T> sf[kBatch], sh[kBatch];
-      static_for<0, kBatch>([&](auto k) {
-        constexpr int I = g * kBatch + k;
-        if constexpr (I < Q) {
-          gather<T, ACT, I, (I != 0)>(fin + I * S, N, sf[k]);
-          if constexpr (WH) gather<T, ACT, I, false>(hin + I * S, N, sh[k]);
-        }
-      });
-      static_for<0, kBatch>([&](auto k) {
-        constexpr int I = g * kBatch + k;
-        if constexpr (I < Q) {
-          T dD, ns;
-          stream_terms<T, ACT, I, (I != 0)>(sf[k], fc[I], dtv, dD, ns);
-          if constexpr (I != 0) fc[I] = (fc[I] - dD) + kap * (ns - NA2 * fc[I]);
-          else fc[I] = fc[I] - dD;
-          if constexpr (WH) {
-            T dH, nh;
-            stream_terms<T, ACT, I, false>(sh[k], hc[I], dtv, dH, nh);
-            hc[I] = hc[I] - dH;
-          }
-        }
-      });
+    stream_all([&](auto I, const Sten<T>& sfI, const Sten<T>& shI) {
+      T dD, ns;
+      stream_terms<T, ACT, I, (I != 0)>(sfI, fc[I], dtv, dD, ns);
+      if constexpr (I != 0) fc[I] = (fc[I] - dD) + kap * (ns - NA2 * fc[I]);
+      else fc[I] = fc[I] - dD;
+      if constexpr (WH) {
+        T dH, nh;
+        stream_terms<T, ACT, I, false>(shI, hc[I], dtv, dH, nh);
+        hc[I] = hc[I] - dH;
+      }
     });
     double E, Mx, My, Mz, N0;
     moments64<T, WH>(P, [&](auto I) { return fc[I]; }, [&](auto I) { return hc[I]; }, E, Mx, My,
@@ -656,17 +878,17 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
     if (P.guard) {
       double thf, thh;
       fired = guard_eval<WH>(P, E, Mx, My, Mz, N0, thf, thh, F);
-      count_events(guard_ptr, fired);
+      count_events(guard_ptr, fired && real);
     }
     if (!fired) ok = recover<WH>(E, Mx, My, Mz, N0, F);
-    flag_bad(bad_ptr, !ok, step_idx);
+    flag_bad(bad_ptr, !ok && real, step_idx);
     double K[10];
     feq_coeffs(P, F.eps, F.ux, F.uy, F.uz, F.g2, K);
     T Kt[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k) Kt[k] = static_cast<T>(K[k]);
     static_for<0, Q>(
-        [&](auto I) { stb_nt(fout + I * S, cb, static_cast<T>(weight(I)) * bracket<I>(Kt)); });
+        [&](auto I) { stb_nt(fout + I * S, cbs, static_cast<T>(weight(I)) * bracket<I>(Kt)); });
     if constexpr (WH) {
       double H[10];
       heq_coeffs(P, F.n, F.ux, F.uy, F.uz, F.gam, H);
@@ -674,19 +896,19 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
 #pragma unroll
       for (int k = 0; k < 10; ++k) Ht[k] = static_cast<T>(H[k]);
       static_for<0, Q>(
-          [&](auto I) { stb_nt(hout + I * S, cb, static_cast<T>(wprime<I>(P)) * bracket<I>(Ht)); });
+          [&](auto I) { stb_nt(hout + I * S, cbs, static_cast<T>(wprime<I>(P)) * bracket<I>(Ht)); });
     }
     return;
   } else {
-    const double pe = ldb_nt(h0, cd), pux = ldb_nt(h1, cd), puy = ldb_nt(h2, cd),
-                 puz = ldb_nt(h3, cd), pn = ldb_nt(h4, cd);
+    const double pe = ldb_nt(h0, cdl), pux = ldb_nt(h1, cdl), puy = ldb_nt(h2, cdl),
+                 puz = ldb_nt(h3, cdl), pn = ldb_nt(h4, cdl);
     // 1-2: moments and fields at time t.
     double E, Mx, My, Mz, N0;
     moments64<T, WH>(P, [&](auto I) { return fc[I]; }, [&](auto I) { return hc[I]; }, E, Mx, My,
                      Mz, N0);
     Fields F;
     const bool ok = recover<WH>(E, Mx, My, Mz, N0, F);
-    flag_bad(bad_ptr, !ok, step_idx);
+    flag_bad(bad_ptr, !ok && real, step_idx);
 
     // 3: the source omega (2 f^eq(t) - f^eq(t - dt)) / (1 + omega) as one
     // coefficient set, computed in FP64 and rounded once to T.
@@ -710,12 +932,14 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
 #pragma unroll
       for (int k = 0; k < 10; ++k) Ht[k] = static_cast<T>(src * (2.0 * H[k] - Hp[k]));
     }
-    double* __restrict__ w0 = hist;
-    stb_nt(w0, cd, F.eps);
-    stb_nt(w0 + NC, cd, F.ux);
-    stb_nt(w0 + 2 * NC, cd, F.uy);
-    stb_nt(w0 + 3 * NC, cd, F.uz);
-    stb_nt(w0 + 4 * NC, cd, F.n);
+    if (real) {
+      double* __restrict__ w0 = hist;
+      stb_nt(w0, cd, F.eps);
+      stb_nt(w0 + NC, cd, F.ux);
+      stb_nt(w0 + 2 * NC, cd, F.uy);
+      stb_nt(w0 + 3 * NC, cd, F.uz);
+      stb_nt(w0 + 4 * NC, cd, F.n);
+    }
 
     const T tinv = static_cast<T>(inv1p);
     const T kinv = static_cast<T>(kappa_d * inv1p);
@@ -724,40 +948,27 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
     // 4-5: limited streaming, bulk term (f only, lambda_0 = 0) and implicit
     // collision, Eq. (57); new moments accumulated for the guard's gate.
     T gE = T(0), gX = T(0), gY = T(0), gZ = T(0), gN = T(0), gA = T(0), gAh = T(0);
-    static_for<0, kNumBatches>([&](auto g) {
-      Sten<T> sf[kBatch], sh[kBatch];
-      static_for<0, kBatch>([&](auto k) {
-        constexpr int I = g * kBatch + k;
-        if constexpr (I < Q) {
-          gather<T, ACT, I, (I != 0)>(fin + I * S, N, sf[k]);
-          if constexpr (WH) gather<T, ACT, I, false>(hin + I * S, N, sh[k]);
-        }
-      });
-      static_for<0, kBatch>([&](auto k) {
-        constexpr int I = g * kBatch + k;
-        if constexpr (I < Q) {
-          constexpr Vel e = vel(I);
-          T dD, ns;
-          stream_terms<T, ACT, I, (I != 0)>(sf[k], fc[I], dtv, dD, ns);
-          T v = (fc[I] - dD) * tinv + static_cast<T>(weight(I)) * bracket<I>(Kt);
-          if constexpr (I != 0) v += kinv * (ns - NA2 * fc[I]);
-          stb_nt(fout + I * S, cb, v);
-          gE += v;
-          gA += fabs(v);
-          if constexpr (e.x != 0) gX += T(e.x) * v;
-          if constexpr (e.y != 0) gY += T(e.y) * v;
-          if constexpr (e.z != 0) gZ += T(e.z) * v;
-          if constexpr (WH) {
-            T dH, nh;
-            stream_terms<T, ACT, I, false>(sh[k], hc[I], dtv, dH, nh);
-            const T wpi = I == 0 ? wp[0] : (I <= 6 ? wp[1] : wp[2]);
-            const T hv = (hc[I] - dH) * tinv + wpi * bracket<I>(Ht);
-            stb_nt(hout + I * S, cb, hv);
-            gN += hv;
-            gAh += fabs(hv);
-          }
-        }
-      });
+    stream_all([&](auto I, const Sten<T>& sfI, const Sten<T>& shI) {
+      constexpr Vel e = vel(I);
+      T dD, ns;
+      stream_terms<T, ACT, I, (I != 0)>(sfI, fc[I], dtv, dD, ns);
+      T v = (fc[I] - dD) * tinv + static_cast<T>(weight(I)) * bracket<I>(Kt);
+      if constexpr (I != 0) v += kinv * (ns - NA2 * fc[I]);
+      stb_nt(fout + I * S, cbs, v);
+      gE += v;
+      gA += fabs(v);
+      if constexpr (e.x != 0) gX += T(e.x) * v;
+      if constexpr (e.y != 0) gY += T(e.y) * v;
+      if constexpr (e.z != 0) gZ += T(e.z) * v;
+      if constexpr (WH) {
+        T dH, nh;
+        stream_terms<T, ACT, I, false>(shI, hc[I], dtv, dH, nh);
+        const T wpi = I == 0 ? wp[0] : (I <= 6 ? wp[1] : wp[2]);
+        const T hv = (hc[I] - dH) * tinv + wpi * bracket<I>(Ht);
+        stb_nt(hout + I * S, cbs, hv);
+        gN += hv;
+        gAh += fabs(hv);
+      }
     });
 
     // Guard: gate in storage precision with a rounding margin, decide and
@@ -767,17 +978,17 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
       const T r2 = static_cast<T>(P.r * P.r), rca = static_cast<T>(P.rca);
       const T Eg = r2 * gE, mrg = tol * r2 * gA;
       const T Mg = rca * sqrt(gX * gX + gY * gY + gZ * gZ);
-      bool need = !(Eg > mrg) || (Mg + mrg > static_cast<T>(P.m1) * (Eg - mrg));
+      bool need = real && (!(Eg > mrg) || (Mg + mrg > static_cast<T>(P.m1) * (Eg - mrg)));
       if constexpr (WH) {
         const T Ng = static_cast<T>(P.r) * gN;
-        need = need ||
-               !(Ng > static_cast<T>(2.0 * P.efloor * P.gmax) + tol * static_cast<T>(P.r) * gAh);
+        need = need || (real && !(Ng > static_cast<T>(2.0 * P.efloor * P.gmax) +
+                                           tol * static_cast<T>(P.r) * gAh));
       }
       bool fired = false;
       if (need) {
         double E2, Mx2, My2, Mz2, N02;
-        moments64<T, WH>(P, [&](auto I) { return ldb(fout + I * S, cb); },
-                         [&](auto I) { return ldb(hout + I * S, cb); }, E2, Mx2, My2, Mz2, N02);
+        moments64<T, WH>(P, [&](auto I) { return ldb(fout + I * S, cbs); },
+                         [&](auto I) { return ldb(hout + I * S, cbs); }, E2, Mx2, My2, Mz2, N02);
         double thf, thh;
         Fields G;
         fired = guard_eval<WH>(P, E2, Mx2, My2, Mz2, N02, thf, thh, G);
@@ -786,16 +997,16 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
           feq_coeffs(P, G.eps, G.ux, G.uy, G.uz, G.g2, Kg);
           static_for<0, Q>([&](auto I) {
             const double ge = weight(I) * bracket<I>(Kg);
-            const double v = static_cast<double>(ldb(fout + I * S, cb));
-            stb(fout + I * S, cb, static_cast<T>(ge + thf * (v - ge)));
+            const double v = static_cast<double>(ldb(fout + I * S, cbs));
+            stb(fout + I * S, cbs, static_cast<T>(ge + thf * (v - ge)));
           });
           if constexpr (WH) {
             double Hg[10];
             heq_coeffs(P, G.n, G.ux, G.uy, G.uz, G.gam, Hg);
             static_for<0, Q>([&](auto I) {
               const double ge = wprime<I>(P) * bracket<I>(Hg);
-              const double v = static_cast<double>(ldb(hout + I * S, cb));
-              stb(hout + I * S, cb, static_cast<T>(ge + thh * (v - ge)));
+              const double v = static_cast<double>(ldb(hout + I * S, cbs));
+              stb(hout + I * S, cbs, static_cast<T>(ge + thh * (v - ge)));
             });
           }
         }
