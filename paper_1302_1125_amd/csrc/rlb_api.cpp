@@ -169,9 +169,9 @@ void fill_params(rlb_ctx* x) {
   p.nty = (c.ny + p.tile_y - 1) / p.tile_y;
   p.ntiles = static_cast<long long>(p.ntx) * p.nty * c.nz;
   // Pencil shape: the largest divisors of ntx / nty not above the targets
-  // (3D: 8 x 4 tiles = 512 x 16 cells marched in z; 2D: strips 16 tiles
+  // (3D: 8 x 3 tiles = 512 x 12 cells marched in z; 2D: strips 16 tiles
   // wide), chosen by measurement on MI355X.
-  int want_w = c.nz > 1 ? 8 : 16, want_h = c.nz > 1 ? 4 : 1 << 30;
+  int want_w = c.nz > 1 ? 8 : 16, want_h = c.nz > 1 ? 3 : 1 << 30;
   if (const char* e = std::getenv("RLB_PENCIL")) {  // tuning override "pw,ph"
     int a = 0, b = 0;
     if (std::sscanf(e, "%d,%d", &a, &b) == 2 && a > 0 && b > 0) {

@@ -355,10 +355,20 @@ constexpr int kTY = kBlock / 64;   // rows per tile
 constexpr int kLW = 64 + 4;        // LDS row: x0 - 2 .. x0 + 65
 constexpr int kLH = kTY + 4;       // LDS rows: y0 - 2 .. y0 + kTY + 1
 
-template <typename T, bool WH>
+#ifndef RLB_STAGES_3D
+#define RLB_STAGES_3D 4
+#endif
+#ifndef RLB_STAGES_2D
+#define RLB_STAGES_2D 2
+#endif
+template <typename T, bool WH, int ACT>
 struct Stages {
-  static constexpr int n = (WH && sizeof(T) == 8) ? 4 : 2;   // stages per step
+  // stages per step (measured on MI355X: smaller stages keep the 3D working
+  // set of a tile's neighbourhood in L2)
+  static constexpr int n =
+      (WH && sizeof(T) == 8) ? (ACT == 7 ? 8 : 4) : (ACT == 7 ? RLB_STAGES_3D : RLB_STAGES_2D);
   static constexpr int pops = (Q + n - 1) / n;               // populations per stage
+  static constexpr int count = (Q + pops - 1) / pops;        // non-empty stages
   static constexpr int arrays = (WH ? 2 : 1) * pops;         // LDS arrays per stage
 };
 
@@ -810,7 +820,7 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
     if constexpr (WH) hc[I] = ldb(hin + I * S, cl);
   });
   // LDS tiles of a stage (2D/3D)
-  __shared__ T lds[ACT != 1 ? Stages<T, WH>::arrays : 1][kLH][kLW];
+  __shared__ T lds[ACT != 1 ? Stages<T, WH, ACT>::arrays : 1][kLH][kLW];
 
   const T dtv = static_cast<T>(P.dtv);
   constexpr T NA2 = T(2 * n_axes<ACT>());
@@ -824,7 +834,7 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
   // from the arrays (1D, in batches).
   auto stream_all = [&](auto&& per_pop) {
     if constexpr (ACT != 1) {
-      constexpr int NS = Stages<T, WH>::n, PP = Stages<T, WH>::pops;
+      constexpr int NS = Stages<T, WH, ACT>::count, PP = Stages<T, WH, ACT>::pops;
       static_for<0, NS>([&](auto st) {
         constexpr int S0 = st * PP;
         constexpr int S1 = S0 + PP < Q ? S0 + PP : Q;
