@@ -3,20 +3,24 @@
 //
 // Data layout (HBM): populations structure-of-arrays f[i][cell] and
 // h[i][cell] with cell = x + nx (y + ny z) and a per-population stride that
-// leaves six face slots after the cells (rlb_internal.h); two copies
-// (ping-pong).  The fields of the previous step hist[k][cell] (FP64,
-// k = eps, ux, uy, uz, n) are read and rewritten in place by their cell.
+// leaves six face slots and a trash slot after the cells (rlb_internal.h);
+// two copies (ping-pong).  The fields of the previous step hist[k][cell]
+// (FP64, k = eps, ux, uy, uz, n) are read and rewritten in place by their cell.
 //
-// One fused kernel per step, one thread per cell.  The thread forms its
-// moments (FP64 accumulation), recovers the fields in FP64 and builds the
-// equilibrium coefficients in FP64; then, one population at a time, it
-// loads the star stencil (absolute neighbour indices precomputed once per
-// cell, boundary conditions folded into them), evaluates the minmod-limited
-// flux divergence, the bulk Laplacian and the implicit collision in the
-// storage precision and stores the result at once, so only the centre
-// values and the coefficient sets stay live.  The admissibility guard is
-// gated by a cheap storage-precision test of the new moments with a
-// rounding margin, and re-decided in FP64 from the stored values.
+// One fused kernel per step, one thread per cell, one workgroup per tile
+// (64 x 4 cells in 2D/3D, 256 cells in 1D).  The thread loads the 38 centre
+// values of its cell, forms the moments (FP64 accumulation), recovers the
+// fields and builds the equilibrium coefficients in FP64.  In 2D/3D the
+// tile's centre values, one halo row per wavefront and the halo cells of
+// each row are then staged in LDS a few populations at a time, so that every
+// x and y neighbour of the star stencil is an LDS read (z neighbours are
+// global loads); in 1D the neighbours are global loads through precomputed,
+// boundary-aware offsets.  Per population the thread evaluates the
+// minmod-limited flux divergence, the bulk Laplacian and the implicit
+// collision in the storage precision and stores the result at once.  The
+// admissibility guard is gated by a cheap storage-precision test of the new
+// moments with a rounding margin, and re-decided in FP64 from the stored
+// values.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
