@@ -107,6 +107,42 @@ def test_random_state_fp64(rlb, shape, euler):
     _assert_fp64(errs)
 
 
+# Staged tiles (2D/3D): x and y neighbours come from LDS tiles of 64 x 4
+# cells; lanes past the x or y end hold boundary-mapped values and obstacle
+# lanes stay in the tile.  Grids that are not tile multiples, every boundary
+# condition on x and y, and an obstacle block straddling a tile boundary.
+_P, _F, _O = W.BC_PERIODIC, W.BC_FIXED, W.BC_OUTFLOW
+
+
+@pytest.mark.parametrize("shape,bc,obstacle", [
+    ((1, 37, 131), [_P, _P, _F, _O], False),
+    ((1, 37, 131), [_O, _F, _P, _P], True),
+    ((1, 6, 70), [_F, _O, _P, _P], True),
+    ((7, 9, 67), [_P, _P, _P, _P, _P, _P], False),
+    ((7, 9, 67), [_F, _O, _P, _P, _O, _F], True),
+    ((5, 14, 5), [_P, _P, _F, _O, _P, _P], False),
+])
+def test_staged_tile_edges_fp64(rlb, shape, bc, obstacle):
+    nz, ny, nx = shape
+    w = W.random_smooth_state(nx, ny, nz, seed=57, with_density=True, alpha=0.15,
+                              tau_mode=W.TAU_ETA_OVER_S, eta_over_s=0.05, dt=0.15)
+    bc = list(bc) + [_P] * (6 - len(bc))
+    faces = [[3.0 + 0.1 * k, 0.05 * (k - 2), -0.03, 0.02, 1.0 + 0.05 * k] for k in range(6)]
+    w = w.copy_with(bc=bc, face_states=faces)
+    if obstacle:
+        m = np.zeros((nz, ny, nx), np.uint8)
+        m[:, 1:4, max(nx // 2 - 3, 0):nx // 2 + 3] = 1   # across x = 64 for nx >= 128
+        m[:, ny - 3:ny - 1, 60 % nx:(60 % nx) + 6] = 1  # across x = 64 near the y end
+        w.obstacle = m
+    _case("staged edges", w, 20)
+    g, gs = _run_gpu(rlb, w, 20)
+    o, orc = _run_oracle(w, 20)
+    assert gs.guard_events == orc.guard_events
+    errs = field_errors(g, o)
+    print(shape, bc, obstacle, errs)
+    _assert_fp64(errs)
+
+
 # The guarded shock-cloud, blast-wave and colliding-slab workloads are
 # chaotic: a one-ulp perturbation of the oracle's own input grows to O(1)
 # within ~80-120 (cloud), ~60 (blast, 1e-7) and ~50 (slabs, 1e-4) steps.
