@@ -60,6 +60,10 @@ def make_workload(name: str, precision: int):
         w = W.colliding_slabs_1d(precision=precision)
     elif name == "shock_tube_1d":
         w = W.shock_tube_1d(precision=precision)
+    elif name.startswith("shock_cloud_3d"):
+        # shock_cloud_3d_{weak,strong}[_viscous]
+        parts = name.split("_")
+        w = W.shock_cloud_3d(regime=parts[3], viscous=name.endswith("_viscous"), precision=precision)
     else:
         raise SystemExit(f"unknown workload {name}")
     return w
@@ -142,6 +146,10 @@ def cpu_baseline(workload: str, precision: int, budget_s: float):
     elif workload == "shock_cloud_2d":
         w = W.shock_cloud_2d(nx=512, ny=256, precision=precision)
         sample = "shock_cloud_2d recipe at 512x256"
+    elif workload.startswith("shock_cloud_3d"):
+        w = W.shock_cloud_3d(nx=100, ny=50, nz=50, regime=workload.split("_")[3],
+                             viscous=workload.endswith("_viscous"), precision=precision)
+        sample = f"{workload} recipe at 100x50x50"
     else:
         w = make_workload(workload, precision)
         sample = f"{workload} full grid"
@@ -297,7 +305,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="blast_wave_3d",
-                    choices=["blast_wave_3d", "shock_cloud_2d", "colliding_slabs_1d", "shock_tube_1d"])
+                    choices=["blast_wave_3d", "shock_cloud_2d", "colliding_slabs_1d", "shock_tube_1d",
+                             "shock_cloud_3d_weak", "shock_cloud_3d_strong",
+                             "shock_cloud_3d_weak_viscous", "shock_cloud_3d_strong_viscous"])
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -718,12 +718,16 @@ __device__ __forceinline__ void moments64(const StepParams& P, LF&& fval, LH&& h
 #ifndef RLB_OCC_F32
 #define RLB_OCC_F32 3
 #endif
+#ifndef RLB_OCC_F32_3D
+#define RLB_OCC_F32_3D RLB_OCC_F32
+#endif
 #ifndef RLB_OCC_F64
 #define RLB_OCC_F64 2
 #endif
-template <typename T>
+template <typename T, int ACT>
 struct Occ {
-  static constexpr int value = sizeof(T) == 4 ? RLB_OCC_F32 : RLB_OCC_F64;
+  static constexpr int value =
+      sizeof(T) == 4 ? (ACT == 7 ? RLB_OCC_F32_3D : RLB_OCC_F32) : RLB_OCC_F64;
 };
 template <int ACT>
 struct Batch {
@@ -736,7 +740,7 @@ struct Batch {
 // bulk term and implicit collision (Eq. (57)) or Euler update -> guard.
 // ---------------------------------------------------------------------------
 template <typename T, int ACT, bool WH, bool EULER, bool SEG>
-__global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
+__global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
     const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ hin,
     T* __restrict__ hout, double* __restrict__ hist, const uint8_t* __restrict__ obst,
     const StepParams P) {
@@ -871,21 +875,35 @@ __global__ __launch_bounds__(kBlock, Occ<T>::value) void k_step(
   if constexpr (EULER) {
     // Streaming and bulk term without collision, then f := f^eq of the
     // post-streaming moments (Sec. III, inviscid case).
+    // The post-streaming populations are only needed through their moments:
+    // they are summed in FP64 as they are produced (canonical order, as in
+    // moments64), so none of them stays live across the stages.
     const T kap = static_cast<T>(kappa_d);
+    double m0 = 0.0, mx = 0.0, my = 0.0, mz = 0.0, mh = 0.0;
     stream_all([&](auto I, const Sten<T>& sfI, const Sten<T>& shI) {
+      constexpr Vel e = vel(I);
       T dD, ns;
       stream_terms<T, ACT, I, (I != 0)>(sfI, fc[I], dtv, dD, ns);
-      if constexpr (I != 0) fc[I] = (fc[I] - dD) + kap * (ns - NA2 * fc[I]);
-      else fc[I] = fc[I] - dD;
+      T v;
+      if constexpr (I != 0) v = (fc[I] - dD) + kap * (ns - NA2 * fc[I]);
+      else v = fc[I] - dD;
+      const double vd = static_cast<double>(v);
+      m0 += vd;
+      if constexpr (e.x != 0) mx += double(e.x) * vd;
+      if constexpr (e.y != 0) my += double(e.y) * vd;
+      if constexpr (e.z != 0) mz += double(e.z) * vd;
       if constexpr (WH) {
         T dH, nh;
         stream_terms<T, ACT, I, false>(shI, hc[I], dtv, dH, nh);
-        hc[I] = hc[I] - dH;
+        mh += static_cast<double>(hc[I] - dH);
+        asm volatile("" : "+v"(mh));
       }
+      // keep the sums current: otherwise the compiler defers them past the
+      // stage barriers and keeps every stencil value live (register spills)
+      asm volatile("" : "+v"(m0), "+v"(mx), "+v"(my), "+v"(mz));
     });
-    double E, Mx, My, Mz, N0;
-    moments64<T, WH>(P, [&](auto I) { return fc[I]; }, [&](auto I) { return hc[I]; }, E, Mx, My,
-                     Mz, N0);
+    const double E = P.r * P.r * m0, Mx = P.rca * mx, My = P.rca * my, Mz = P.rca * mz,
+                 N0 = P.r * mh;
     Fields F;
     bool ok = true;
     bool fired = false;

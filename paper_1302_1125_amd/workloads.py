@@ -222,6 +222,46 @@ def blast_wave_3d(n=384, steps=2000, radius=32.0, energy_ratio=1e3, eta_over_s=0
     return w
 
 
+def shock_cloud_3d(nx=200, ny=100, nz=100, regime="weak", viscous=False, steps=None,
+                   precision=MIXED, nu=NU_DEFAULT, alpha=0.2, dt=0.15, tau=1.0,
+                   guard_umax=0.999) -> Workload:
+    """The paper's 3D astrophysical application (Sec. III): a Riemann
+    discontinuity at the plane x = 65 of a 200 x 100 x 100 lattice drives a
+    shock into a solid spherical cloud of radius 10 centred at (100, 50, 50).
+    Driver state (n0, T0) on the inlet side x <= 65 (the reading also taken
+    for the 2D cloud), ambient (n1, T1) = (1, 1) beyond; p = n T, eps = 3 p.
+    The cloud is an obstacle held at the equilibrium of (n1, T1, u = 0); the
+    x = 0 face is an inlet fixed to the driver equilibrium, the other faces
+    are open (outflow).  regime 'weak': T0 = 2.71 T1, n0 = 0.9 n1 (the
+    paper's beta ~ 0.2); 'strong': T0 = 54.77 T1, n0 = 10.95 n1 (beta ~ 0.9).
+    Inviscid: Euler mode, alpha = 0.2, dt/dx = 0.15, 1000 steps; viscous:
+    uniform tau = 1, 600 steps.  Geometry scales with (nx, ny, nz)."""
+    T0, n0 = (2.71, 0.9) if regime == "weak" else (54.77, 10.95)
+    e0 = 3.0 * n0 * T0
+    sx, sy, sz = nx / 200.0, ny / 100.0, nz / 100.0
+    shape = (nz, ny, nx)
+    Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    drive = X <= 65.0 * sx
+    r = 10.0 * min(sx, sy, sz)
+    cloud = (X - 100.0 * sx) ** 2 + (Y - 50.0 * sy) ** 2 + (Z - 50.0 * sz) ** 2 <= r * r
+    eps = np.where(drive & ~cloud, e0, 3.0)
+    n = np.where(drive & ~cloud, n0, 1.0)
+    if steps is None:
+        steps = 600 if viscous else 1000
+    name = f"shock_cloud_3d_{regime}" + ("_viscous" if viscous else "")
+    w = Workload(name, nx, ny, nz, steps, precision=precision,
+                 collision=COLL_IMPLICIT if viscous else COLL_EULER,
+                 tau_mode=TAU_UNIFORM, tau=tau, alpha=alpha, with_density=True, nu=nu, dt=dt,
+                 bc=[BC_FIXED] + [BC_OUTFLOW] * 5,
+                 face_states=[[e0, 0.0, 0.0, 0.0, n0]] + [[3.0, 0.0, 0.0, 0.0, 1.0]] * 5,
+                 guard_umax=guard_umax)
+    w.eps = eps.astype(np.float64)
+    w.ux, w.uy, w.uz = _zeros(shape), _zeros(shape), _zeros(shape)
+    w.n = n.astype(np.float64)
+    w.obstacle = cloud.astype(np.uint8)
+    return w
+
+
 def uniform_state(nx, ny, nz, eps=3.0, u=(0.0, 0.0, 0.0), n=1.0, **kw) -> Workload:
     """A uniform state (a fixed point of the update under periodic boundaries)."""
     shape = (nz, ny, nx)

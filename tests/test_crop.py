@@ -23,3 +23,10 @@ def test_crop_shock_cloud():
 def test_crop_blast_periodic_3d():
     w = W.blast_wave_3d(n=24, precision=W.FP64)
     _check(w, [(0, 0, 0), (23, 23, 23), (12, 12, 12), (12, 3, 20), (1, 22, 11)], 3)
+
+
+def test_crop_shock_cloud_3d():
+    # inlet at x = 0, outflow on the other five faces, a spherical obstacle
+    w = W.shock_cloud_3d(nx=40, ny=20, nz=20, regime="strong", precision=W.FP64)
+    _check(w, [(0, 0, 0), (19, 19, 39), (10, 10, 20), (10, 10, 13), (10, 12, 22), (3, 17, 1),
+               (19, 0, 38)], 3)

@@ -79,3 +79,13 @@ def test_shock_cloud_2048_mixed(rlb):
 
 def test_shock_cloud_2048_fp64(rlb):
     _compare(rlb, W.shock_cloud_2d(precision=W.FP64), W.FP64, FP64_TOL)
+
+
+@pytest.mark.parametrize("regime", ["weak", "strong"])
+def test_shock_cloud_3d_200x100x100_mixed(rlb, regime):
+    _compare(rlb, W.shock_cloud_3d(regime=regime, precision=W.MIXED), W.MIXED, MIXED_TOL)
+
+
+@pytest.mark.parametrize("regime", ["weak", "strong"])
+def test_shock_cloud_3d_200x100x100_fp64(rlb, regime):
+    _compare(rlb, W.shock_cloud_3d(regime=regime, precision=W.FP64), W.FP64, FP64_TOL)

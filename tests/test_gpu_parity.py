@@ -172,6 +172,24 @@ def test_blast_wave_scaled_fp64(rlb):
     _assert_fp64(errs)
 
 
+# The 3D shock-cloud (Sec. III) at 60 x 30 x 30.  Weak regime: no guard
+# events, long runs stay inside the predictability horizon.  Strong regime:
+# the guard fires at the shock front from about step 25 on; its inviscid
+# variant is compared up to step 30 and the viscous one (horizon > 80 steps)
+# up to step 60, with the guard-event counts compared as integers.
+@pytest.mark.parametrize("regime,viscous,steps", [
+    ("weak", False, 80), ("weak", True, 60), ("strong", False, 30), ("strong", True, 60)])
+def test_shock_cloud_3d_scaled_fp64(rlb, regime, viscous, steps):
+    w = W.shock_cloud_3d(nx=60, ny=30, nz=30, regime=regime, viscous=viscous, precision=W.FP64)
+    _case(f"{w.name} scaled", w, steps)
+    g, gs = _run_gpu(rlb, w, steps)
+    o, orc = _run_oracle(w, steps)
+    assert gs.guard_events == orc.guard_events
+    errs = field_errors(g, o)
+    print(errs, "guard events gpu", gs.guard_events, "oracle", orc.guard_events)
+    _assert_fp64(errs)
+
+
 def test_colliding_slabs_fp64(rlb):
     w = W.colliding_slabs_1d(steps=20)
     _case("colliding_slabs_1d", w, 20)
@@ -183,10 +201,12 @@ def test_colliding_slabs_fp64(rlb):
     _assert_fp64(errs)
 
 
-@pytest.mark.parametrize("which", ["shock_cloud", "blast", "tube"])
+@pytest.mark.parametrize("which", ["shock_cloud", "blast", "tube", "shock_cloud_3d"])
 def test_mixed_precision_errors(rlb, which):
     if which == "shock_cloud":
         w, steps = W.shock_cloud_2d(nx=256, ny=128, steps=20), 20
+    elif which == "shock_cloud_3d":
+        w, steps = W.shock_cloud_3d(nx=60, ny=30, nz=30, regime="weak"), 80
     elif which == "blast":
         w, steps = W.blast_wave_3d(n=32, steps=30), 30
     else:

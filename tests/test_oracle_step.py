@@ -380,3 +380,42 @@ def test_guarded_shock_cloud_predictability_horizon():
     assert a.step(90) == 0 and b.step(90) == 0
     e120 = field_errors(b.fields(), a.fields())
     assert e120["eps"] > 1e3 * max(e30["eps"], 1e-16)
+
+
+def test_shock_cloud_3d_recipe_geometry():
+    """Sec. III set-up: plane discontinuity at x = 65 of 200 x 100 x 100, a
+    sphere of radius 10 at (100, 50, 50); p = n T, eps = 3 p on both sides."""
+    for regime, T0, n0 in (("weak", 2.71, 0.9), ("strong", 54.77, 10.95)):
+        w = W.shock_cloud_3d(regime=regime, precision=W.FP64)
+        assert w.shape == (100, 100, 200)
+        m = w.obstacle.astype(bool)
+        assert abs(m.sum() - 4.0 / 3.0 * np.pi * 1000.0) < 0.02 * 4.0 / 3.0 * np.pi * 1000.0
+        assert m[50, 50, 100] and m[50, 50, 110] and not m[50, 50, 111]
+        np.testing.assert_allclose(w.eps[:, :, :66][~m[:, :, :66]], 3.0 * n0 * T0)
+        np.testing.assert_allclose(w.eps[:, :, 66:], 3.0)
+        np.testing.assert_allclose(w.n[:, :, 66:], 1.0)
+        np.testing.assert_allclose(w.face_states[0], [3.0 * n0 * T0, 0, 0, 0, n0])
+        assert list(w.bc) == [W.BC_FIXED] + [W.BC_OUTFLOW] * 5
+
+
+def test_shock_cloud_3d_far_rows_equal_the_1d_riemann_run():
+    """Away from the sphere's dependency cone the 3D shock-cloud is a plane
+    Riemann problem: rows with transverse outflow faces equal a 1D run of the
+    same driver/ambient states to rounding."""
+    steps = 3
+    w = W.shock_cloud_3d(nx=60, ny=30, nz=30, regime="strong", precision=W.FP64)
+    o = oracle_for(w)
+    assert o.step(steps) == 0
+    full = o.fields()
+    w1 = w.copy_with(ny=1, nz=1, bc=[W.BC_FIXED, W.BC_OUTFLOW] + [W.BC_PERIODIC] * 4)
+    w1.eps, w1.ux, w1.uy, w1.uz = (a[:1, :1, :].copy() for a in (w.eps, w.ux, w.uy, w.uz))
+    w1.n, w1.obstacle = w.n[:1, :1, :].copy(), np.zeros((1, 1, 60), np.uint8)
+    o1 = oracle_for(w1)
+    assert o1.step(steps) == 0
+    row = o1.fields()
+    # sphere: radius 3 around (30, 15, 15); dependency cone 2 k + 2 = 8 cells
+    for z, y in ((0, 0), (29, 29), (15, 3), (2, 27)):
+        for a, b in zip(full, row):
+            np.testing.assert_allclose(a[z, y, :], b[0, 0, :], rtol=1e-13, atol=1e-15)
+    # the shock has moved: the run is not trivially at its initial state
+    assert not np.allclose(row[0][0, 0, 15:25], w1.eps[0, 0, 15:25], rtol=1e-3)
