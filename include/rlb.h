@@ -64,7 +64,10 @@ typedef struct {
   uint32_t struct_size; /* = sizeof(rlb_config) (ABI check)                 */
   int32_t nx, ny, nz;   /* grid; ny == 1 requires nz == 1; nx >= 2.  Axes
                            of size 1 must be periodic (quasi-1D / 2D).
-                           At most 2^28 - 128 cells in all.                 */
+                           At most 2^28 - 128 cells in all, counted as
+                           stored: a 2D/3D grid takes (nx rounded up to a
+                           multiple of 64) x (ny rounded up to a multiple
+                           of 4) x nz cells on the device.                  */
   int32_t precision;    /* RLB_FP64: populations stored and updated in FP64.
                            RLB_MIXED: populations stored and streamed in
                            FP32; moments accumulated in FP64; recovery and

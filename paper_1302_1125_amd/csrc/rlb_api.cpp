@@ -40,7 +40,9 @@ struct rlb_ctx {
   int act_mask = 1;
   bool fp64 = true;
   size_t elem = 8;
-  long long ncell = 0;
+  long long ncell = 0;   // dense cells nx * ny * nz
+  int px = 0, py = 0;    // row pitch, rows per plane (rlb::row_pitch, rlb::plane_rows)
+  long long nstore = 0;  // storage cells px * py * nz
   void* f[2] = {nullptr, nullptr};
   void* h[2] = {nullptr, nullptr};
   int cur = 0;
@@ -68,8 +70,10 @@ rlb_status validate(const rlb_config* c) {
   if (c->struct_size != sizeof(rlb_config)) return fail(RLB_E_INVALID_ARG, "struct_size mismatch");
   if (c->nx < 2 || c->ny < 1 || c->nz < 1) return fail(RLB_E_INVALID_ARG, "grid: nx >= 2, ny, nz >= 1");
   if (c->ny == 1 && c->nz != 1) return fail(RLB_E_INVALID_ARG, "ny == 1 requires nz == 1");
-  const long long nc = static_cast<long long>(c->nx) * c->ny * c->nz;
-  if (nc > rlb::kMaxCells) return fail(RLB_E_INVALID_ARG, "grid too large (at most 2^28 - 128 cells)");
+  const long long nc = static_cast<long long>(rlb::row_pitch(c->nx, c->ny)) * rlb::plane_rows(c->ny) * c->nz;
+  if (nc > rlb::kMaxCells)
+    return fail(RLB_E_INVALID_ARG,
+                "grid too large (at most 2^28 - 128 cells, nx padded to 64 and ny to 4 in 2D/3D)");
   if (c->precision != RLB_FP64 && c->precision != RLB_MIXED) return fail(RLB_E_INVALID_ARG, "precision");
   if (c->collision != RLB_COLL_IMPLICIT && c->collision != RLB_COLL_EULER)
     return fail(RLB_E_INVALID_ARG, "collision");
@@ -104,11 +108,12 @@ rlb_status validate(const rlb_config* c) {
 
 uint64_t footprint(const rlb_config* c) {
   const uint64_t nc = static_cast<uint64_t>(c->nx) * c->ny * c->nz;
-  const uint64_t ps = static_cast<uint64_t>(rlb::population_stride(static_cast<long long>(nc)));
+  const uint64_t ns = static_cast<uint64_t>(rlb::row_pitch(c->nx, c->ny)) * rlb::plane_rows(c->ny) * c->nz;
+  const uint64_t ps = static_cast<uint64_t>(rlb::population_stride(static_cast<long long>(ns)));
   const uint64_t elem = c->precision == RLB_FP64 ? 8 : 4;
   uint64_t b = 2 * rlb::Q * ps * elem;            // f, ping-pong
   if (c->with_density) b += 2 * rlb::Q * ps * elem;
-  b += 5 * nc * 8;                                // previous-step fields
+  b += 5 * ns * 8;                                // previous-step fields
   b += (nc + 255) / 256 * 5 * 8;                  // reduction partials
   b += 6 * 5 * 8 + 4 * 8 + 8 * 8;                 // face states, counters, sums
   return b;
@@ -153,11 +158,13 @@ void fill_params(rlb_ctx* x) {
   const rlb_config& c = x->cfg;
   rlb::StepParams& p = x->base;
   p = rlb::StepParams{};
-  p.ncell = x->ncell;
-  p.pstride = rlb::population_stride(x->ncell);
+  p.ncell = x->nstore;
+  p.pstride = rlb::population_stride(x->nstore);
   p.nx = c.nx;
   p.ny = c.ny;
   p.nz = c.nz;
+  p.px = x->px;
+  p.py = x->py;
   if (c.ny == 1) {
     p.tile_x = rlb::kBlock;
     p.tile_y = 1;
@@ -327,6 +334,9 @@ rlb_status rlb_create(const rlb_config* cfg, void* hip_stream, rlb_ctx** out) {
   x->fp64 = cfg->precision == RLB_FP64;
   x->elem = x->fp64 ? 8 : 4;
   x->ncell = static_cast<long long>(cfg->nx) * cfg->ny * cfg->nz;
+  x->px = rlb::row_pitch(cfg->nx, cfg->ny);
+  x->py = rlb::plane_rows(cfg->ny);
+  x->nstore = static_cast<long long>(x->px) * x->py * cfg->nz;
   x->act_mask = cfg->nz > 1 ? 7 : (cfg->ny > 1 ? 3 : 1);
   if (hip_stream) {
     x->stream = static_cast<hipStream_t>(hip_stream);
@@ -338,14 +348,14 @@ rlb_status rlb_create(const rlb_config* cfg, void* hip_stream, rlb_ctx** out) {
     }
     x->own_stream = true;
   }
-  const size_t pop_bytes = static_cast<size_t>(rlb::Q) * rlb::population_stride(x->ncell) * x->elem;
+  const size_t pop_bytes = static_cast<size_t>(rlb::Q) * rlb::population_stride(x->nstore) * x->elem;
   x->sums_blocks = static_cast<int>((x->ncell + rlb::kBlock - 1) / rlb::kBlock);
   st = RLB_OK;
   for (int k = 0; k < 2 && st == RLB_OK; ++k) {
     st = dalloc(&x->f[k], pop_bytes, "f");
     if (st == RLB_OK && cfg->with_density) st = dalloc(&x->h[k], pop_bytes, "h");
   }
-  if (st == RLB_OK) st = dalloc(&x->hist, 5 * sizeof(double) * x->ncell, "fields");
+  if (st == RLB_OK) st = dalloc(&x->hist, 5 * sizeof(double) * x->nstore, "fields");
   if (st == RLB_OK) st = dalloc(&x->face_states, 6 * 5 * sizeof(double), "face_states");
   if (st == RLB_OK) st = dalloc(&x->counters, 4 * sizeof(unsigned long long), "counters");
   if (st == RLB_OK) st = dalloc(&x->sums_partial, static_cast<size_t>(x->sums_blocks) * 5 * sizeof(double), "sums");
@@ -402,19 +412,33 @@ rlb_status rlb_init_fields(rlb_ctx* x, const double* eps, const double* ux, cons
   }
   rlb_status st = set_device(x);
   if (st != RLB_OK) return st;
-  const size_t nb = sizeof(double) * x->ncell;
+  // dense host planes [z][y][x] into device planes of py rows of pitch px
+  const size_t nx = static_cast<size_t>(x->cfg.nx), ny = static_cast<size_t>(x->cfg.ny);
+  const size_t nz = static_cast<size_t>(x->cfg.nz);
+  const size_t px = static_cast<size_t>(x->px), py = static_cast<size_t>(x->py);
+  auto upload = [&](void* dst, const void* src, size_t elem) {
+    if (px == nx && py == ny)
+      return hipMemcpyAsync(dst, src, elem * nx * ny * nz, hipMemcpyHostToDevice, x->stream);
+    hipError_t r = hipSuccess;
+    for (size_t z = 0; z < nz && r == hipSuccess; ++z)
+      r = hipMemcpy2DAsync(static_cast<char*>(dst) + z * py * px * elem, px * elem,
+                           static_cast<const char*>(src) + z * ny * nx * elem, nx * elem, nx * elem, ny,
+                           hipMemcpyHostToDevice, x->stream);
+    return r;
+  };
   const double* src[5] = {eps, ux, uy, uz, wh ? n : nullptr};
   hipError_t e = hipSuccess;
   for (int k = 0; k < 5 && e == hipSuccess; ++k)
-    if (src[k]) e = hipMemcpyAsync(x->hist + k * x->ncell, src[k], nb, hipMemcpyHostToDevice, x->stream);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(fields)");
+    if (src[k]) e = upload(x->hist + k * x->nstore, src[k], sizeof(double));
+  if (e != hipSuccess) return hip_fail(e, "upload(fields)");
   if (obstacle) {
     if (!x->obst) {
-      st = dalloc(&x->obst, static_cast<size_t>(x->ncell), "obstacle");
+      st = dalloc(&x->obst, static_cast<size_t>(x->nstore), "obstacle");
       if (st != RLB_OK) return st;
     }
-    e = hipMemcpyAsync(x->obst, obstacle, static_cast<size_t>(x->ncell), hipMemcpyHostToDevice, x->stream);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(obstacle)");
+    e = hipMemsetAsync(x->obst, 0, static_cast<size_t>(x->nstore), x->stream);
+    if (e == hipSuccess) e = upload(x->obst, obstacle, 1);
+    if (e != hipSuccess) return hip_fail(e, "upload(obstacle)");
   }
   x->cur = 0;
   rlb::StepParams p = x->base;

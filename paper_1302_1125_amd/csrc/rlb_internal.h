@@ -14,20 +14,39 @@ constexpr int kXcds = 8;         // MI355X: 8 XCDs, workgroups dispatched round-
 constexpr int kFaceSlots = 6;    // per population: equilibria of the 6 faces
 constexpr int kBcPeriodic = 0, kBcFixed = 1, kBcOutflow = 2;
 
-// Population arrays hold pstride elements per population: cells
-// [0, ncell) in the order x + nx (y + ny z), then one slot per face
+// Population arrays hold pstride elements per population: storage cells
+// [0, ncell) in the order x + px (y + py z), then one slot per face
 // [ncell, ncell + 6) holding the equilibrium of that face's fixed state
 // (written once at creation in both ping-pong copies).  A neighbour index
 // that crosses a FIXED face points at the face slot, so boundary conditions
 // are pure index mapping inside the step kernel.
-// Elements per population array: the ncell cells, the kFaceSlots face slots,
-// one trash slot (index ncell + kFaceSlots: lanes whose results are discarded
-// store there), padded to a multiple of 64.
+//
+// Padded storage of 2D/3D grids: each x-row holds px = nx rounded up to a
+// multiple of 64 cells and each z-plane py = ny rounded up to a multiple of
+// kBlock / 64 rows, i.e. exactly the cells covered by the 64 x 4 tiles of the
+// step kernel.  Every lane of a ragged tile then owns a storage cell: lanes
+// past the x or y end store their (discarded) results at their own pad cell,
+// in the same coalesced row writes as their neighbours, instead of all lanes
+// of the grid sharing one scratch slot (a single L2 line that serialised
+// those stores: 4x at nx = 200).  Rows also start on 256-byte boundaries.
+// Pad cells are written by those lanes only and never read.  1D grids and the
+// serving arena keep px = nx, py = 1.  ncell here is the storage count
+// px py nz; host fields stay dense [z][y][x].
+constexpr int kRowAlign = 64;
+inline int row_pitch(int nx, int ny) {
+  return ny > 1 ? (nx + kRowAlign - 1) / kRowAlign * kRowAlign : nx;
+}
+inline int plane_rows(int ny) {
+  constexpr int r = kBlock / 64;
+  return ny > 1 ? (ny + r - 1) / r * r : ny;
+}
+// Elements per population array: the ncell storage cells and the kFaceSlots
+// face slots, padded to a multiple of 64.
 inline long long population_stride(long long ncell) {
-  return (ncell + kFaceSlots + 1 + 63) / 64 * 64;
+  return (ncell + kFaceSlots + 63) / 64 * 64;
 }
 
-// Largest grid (or serving arena) in cells.  Kernels address every array by
+// Largest grid (storage cells px py nz) or serving arena in cells.  Kernels address every array by
 // 32-bit byte offsets from a per-array base; with FP64 arrays (populations in
 // FP64 mode, previous-step fields always) 8 * population_stride must stay
 // below 2^31.  The serving arena obeys the same limit.
@@ -41,9 +60,10 @@ struct StepParams {
   void* h_out;
   double* hist;            // [5][ncell]: eps, ux, uy, uz, n of the previous step
   const uint8_t* obst;     // [ncell] or nullptr
-  long long ncell;
+  long long ncell;         // storage cells px * py * nz (pad cells included)
   long long pstride;       // elements per population array (population_stride)
   int nx, ny, nz;
+  int px, py;              // row pitch, rows per plane (row_pitch, plane_rows)
   // Workgroup tiling: tile_x * tile_y == kBlock cells of one z-plane, and a
   // traversal order that keeps stencil reuse inside one XCD's L2.  Tiles are
   // grouped into pencils of pw x ph tiles (pw divides ntx, ph divides nty).
@@ -84,8 +104,8 @@ struct StepParams {
   const int2* tiles;           // per workgroup: (segment id or -1, tile within segment)
   const long long* gstep;      // device: global step at the start of the chunk
   int step_in_chunk;           // offset of this launch within the chunk
-  long long cell0;             // first cell of k_init / k_moments ranges
-  long long range;             // number of cells of k_init / k_moments ranges (0: ncell)
+  long long cell0;             // first (dense) cell of k_init / k_moments ranges
+  long long range;             // number of dense cells of k_init / k_moments ranges
 };
 
 // One independent 1D domain of the batched segment step.  Its cells occupy

@@ -2,9 +2,9 @@
 // Boltzmann update of Mohseni, Mendoza, Succi and Herrmann (arXiv:1302.1125).
 //
 // Data layout (HBM): populations structure-of-arrays f[i][cell] and
-// h[i][cell] with cell = x + nx (y + ny z) and a per-population stride that
-// leaves six face slots and a trash slot after the cells (rlb_internal.h);
-// two copies (ping-pong).  The fields of the previous step hist[k][cell]
+// h[i][cell] with cell = x + px (y + py z) (2D/3D rows and planes padded to
+// the 64 x 4 tiles, rlb_internal.h) and a per-population stride that leaves
+// six face slots after the cells; two copies (ping-pong).  The fields of the previous step hist[k][cell]
 // (FP64, k = eps, ux, uy, uz, n) are read and rewritten in place by their cell.
 //
 // One fused kernel per step, one thread per cell, one workgroup per tile
@@ -257,7 +257,7 @@ __device__ __forceinline__ T dflux_neg(T m1, T c0, T p1, T p2) {
 template <int ACT>
 struct Nbr {
   unsigned c;        // byte offset of the value this lane loads (its cell)
-  unsigned cs;       // byte offset its results are stored at (c, or the trash slot)
+  unsigned cs;       // byte offset its results are stored at (its own storage cell)
   unsigned hr, hx;   // staged tiles: halo row / halo column position this lane loads
   unsigned o[3][4];
 };
@@ -266,8 +266,8 @@ template <typename T, int ACT>
 __device__ __forceinline__ void make_nbr(const StepParams& P, int x, int y, int z, Nbr<ACT>& N) {
   const int co[3] = {x, y, z};
   const int n[3] = {P.nx, P.ny, P.nz};
-  const long long st[3] = {1, P.nx, static_cast<long long>(P.nx) * P.ny};
-  const long long c = x + static_cast<long long>(P.nx) * (y + static_cast<long long>(P.ny) * z);
+  const long long st[3] = {1, P.px, static_cast<long long>(P.px) * P.py};
+  const long long c = x + static_cast<long long>(P.px) * (y + static_cast<long long>(P.py) * z);
   N.c = static_cast<unsigned>(c) * static_cast<unsigned>(sizeof(T));
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -352,8 +352,8 @@ __device__ __forceinline__ T ldb_nt(const T* __restrict__ base, unsigned off) {
 // neighbour is an LDS read.  z neighbours stay global loads.  The arrays go
 // through LDS in stages of a few populations (f and h together).  Lanes of
 // a ragged tile past the x or y end hold the boundary-mapped value of their
-// position, so that every value the tile reads is right; they update
-// nothing (stores go to the trash slot of each array).
+// position, so that every value the tile reads is right; their results go
+// to their own pad cell (never read) and they touch no field or counter.
 // ---------------------------------------------------------------------------
 constexpr int kTY = kBlock / 64;   // rows per tile
 constexpr int kLW = 64 + 4;        // LDS row: x0 - 2 .. x0 + 65
@@ -376,23 +376,23 @@ struct Stages {
   static constexpr int arrays = (WH ? 2 : 1) * pops;         // LDS arrays per stage
 };
 
-// Cell index (or face slot) of position (px, py) of plane z for px in
-// [-2, nx + 1], py in [-2, ny + 1], with the x and y boundary conditions.
-__device__ __forceinline__ long long map_xy(const StepParams& P, int px, int py, int z) {
+// Cell index (or face slot) of position (qx, qy) of plane z for qx in
+// [-2, nx + 1], qy in [-2, ny + 1], with the x and y boundary conditions.
+__device__ __forceinline__ long long map_xy(const StepParams& P, int qx, int qy, int z) {
   const int nx = P.nx, ny = P.ny;
-  if (py < 0 || py >= ny) {
-    const int side = py < 0 ? 0 : 1;
+  if (qy < 0 || qy >= ny) {
+    const int side = qy < 0 ? 0 : 1;
     const int b = P.bc[2 + side];
     if (b == kBcFixed) return P.ncell + 2 + side;
-    py = b == kBcPeriodic ? (py < 0 ? py + ny : py - ny) : (py < 0 ? 0 : ny - 1);
+    qy = b == kBcPeriodic ? (qy < 0 ? qy + ny : qy - ny) : (qy < 0 ? 0 : ny - 1);
   }
-  if (px < 0 || px >= nx) {
-    const int side = px < 0 ? 0 : 1;
+  if (qx < 0 || qx >= nx) {
+    const int side = qx < 0 ? 0 : 1;
     const int b = P.bc[side];
     if (b == kBcFixed) return P.ncell + side;
-    px = b == kBcPeriodic ? (px < 0 ? px + nx : px - nx) : (px < 0 ? 0 : nx - 1);
+    qx = b == kBcPeriodic ? (qx < 0 ? qx + nx : qx - nx) : (qx < 0 ? 0 : nx - 1);
   }
-  return static_cast<long long>(nx) * (py + static_cast<long long>(ny) * z) + px;
+  return static_cast<long long>(P.px) * (qy + static_cast<long long>(P.py) * z) + qx;
 }
 
 // Offsets of a staged tile's lane at (x, y, z) (x, y possibly past the end):
@@ -407,7 +407,8 @@ __device__ __forceinline__ void make_nbr_stg(const StepParams& P, int x, int y, 
   const unsigned sz = static_cast<unsigned>(sizeof(T));
   const long long c = map_xy(P, px, py, z);
   N.c = static_cast<unsigned>(c) * sz;
-  N.cs = N.c;
+  // own storage cell (x < px, y < py: the padded planes cover every tile)
+  N.cs = static_cast<unsigned>(x + static_cast<long long>(P.px) * (y + static_cast<long long>(P.py) * z)) * sz;
   const int y0 = y - w, x0 = x - lane;
   int hy = y0 - 2 + (w < 2 ? w : kTY + w);
   hy = hy < P.ny + 1 ? hy : P.ny + 1;
@@ -416,7 +417,7 @@ __device__ __forceinline__ void make_nbr_stg(const StepParams& P, int x, int y, 
   hxp = hxp < P.nx + 1 ? hxp : P.nx + 1;
   N.hx = lane < 4 ? static_cast<unsigned>(map_xy(P, hxp, py, z)) * sz : N.c;
   if constexpr (axis_on<ACT>(2)) {
-    const long long st = static_cast<long long>(P.nx) * P.ny;
+    const long long st = static_cast<long long>(P.px) * P.py;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int k = j < 2 ? j - 2 : j - 1;
@@ -787,8 +788,6 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
       make_nbr_stg<T, ACT>(P, x, y, z, inside, N);
     }
   }
-  const unsigned trash = static_cast<unsigned>(P.ncell + kFaceSlots) * static_cast<unsigned>(sizeof(T));
-  if (!inside) N.cs = trash;
   bool real = inside;                                       // this lane updates its cell
   const unsigned cl = N.c;                                  // byte offset loaded from
   const unsigned cb = N.cs;                                 // byte offset stored to
@@ -801,25 +800,32 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
   const double* __restrict__ h3 = hist + 3 * NC;
   const double* __restrict__ h4 = hist + 4 * NC;
 
-  // Obstacle cells: held at the equilibrium of their prescribed fields.  In a
-  // staged tile the lane stays (its value is a neighbour) and updates nothing.
+  // Obstacle cells: held at the equilibrium of their prescribed fields (kept
+  // in hist).  1D: written here.  In a staged tile the lane stays (its value
+  // is a neighbour), touches no field or counter, and its regular stores
+  // write that equilibrium (coefficient override below).
+  bool solid = false;
   if (!SEG && obst != nullptr && inside && obst[cl / sizeof(T)] != 0) {
-    const double eps = ldb(h0, cd), ux = ldb(h1, cd), uy = ldb(h2, cd), uz = ldb(h3, cd),
-                 nn = ldb(h4, cd);
-    const double g2 = 1.0 / (1.0 - (ux * ux + uy * uy + uz * uz));
-    double K[10];
-    feq_coeffs(P, eps, ux, uy, uz, g2, K);
-    static_for<0, Q>([&](auto I) { stb(fout + I * S, cl, static_cast<T>(weight(I) * bracket<I>(K))); });
-    if constexpr (WH) {
-      double H[10];
-      heq_coeffs(P, nn, ux, uy, uz, sqrt(g2), H);
+    if constexpr (ACT == 1) {
+      const double eps = ldb(h0, cd), ux = ldb(h1, cd), uy = ldb(h2, cd), uz = ldb(h3, cd),
+                   nn = ldb(h4, cd);
+      const double g2 = 1.0 / (1.0 - (ux * ux + uy * uy + uz * uz));
+      double K[10];
+      feq_coeffs(P, eps, ux, uy, uz, g2, K);
       static_for<0, Q>(
-          [&](auto I) { stb(hout + I * S, cl, static_cast<T>(wprime<I>(P) * bracket<I>(H))); });
+          [&](auto I) { stb(fout + I * S, cl, static_cast<T>(weight(I) * bracket<I>(K))); });
+      if constexpr (WH) {
+        double H[10];
+        heq_coeffs(P, nn, ux, uy, uz, sqrt(g2), H);
+        static_for<0, Q>(
+            [&](auto I) { stb(hout + I * S, cl, static_cast<T>(wprime<I>(P) * bracket<I>(H))); });
+      }
+      return;
     }
-    if constexpr (ACT == 1) return;
+    solid = true;
     real = false;
   }
-  const unsigned cbs = real ? cb : trash;  // obstacle lanes of a staged tile store to the trash slot
+  const unsigned cbs = cb;
 
   T fc[Q];
   T hc[Q];
@@ -914,6 +920,16 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
     }
     if (!fired) ok = recover<WH>(E, Mx, My, Mz, N0, F);
     flag_bad(bad_ptr, !ok && real, step_idx);
+    if (solid) {
+      // obstacle lane: the equilibrium of its prescribed fields
+      F.eps = ldb(h0, cd);
+      F.ux = ldb(h1, cd);
+      F.uy = ldb(h2, cd);
+      F.uz = ldb(h3, cd);
+      F.n = ldb(h4, cd);
+      F.g2 = 1.0 / (1.0 - (F.ux * F.ux + F.uy * F.uy + F.uz * F.uz));
+      F.gam = sqrt(F.g2);
+    }
     double K[10];
     feq_coeffs(P, F.eps, F.ux, F.uy, F.uz, F.g2, K);
     T Kt[10];
@@ -953,8 +969,9 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
       double K[10], Kp[10];
       feq_coeffs(P, F.eps, F.ux, F.uy, F.uz, F.g2, K);
       feq_coeffs(P, pe, pux, puy, puz, pg2, Kp);
+      // obstacle lane: the equilibrium of its prescribed fields (held in hist)
 #pragma unroll
-      for (int k = 0; k < 10; ++k) Kt[k] = static_cast<T>(src * (2.0 * K[k] - Kp[k]));
+      for (int k = 0; k < 10; ++k) Kt[k] = static_cast<T>(solid ? Kp[k] : src * (2.0 * K[k] - Kp[k]));
     }
     T Ht[10];
     if constexpr (WH) {
@@ -962,7 +979,7 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
       heq_coeffs(P, F.n, F.ux, F.uy, F.uz, F.gam, H);
       heq_coeffs(P, pn, pux, puy, puz, sqrt(pg2), Hp);
 #pragma unroll
-      for (int k = 0; k < 10; ++k) Ht[k] = static_cast<T>(src * (2.0 * H[k] - Hp[k]));
+      for (int k = 0; k < 10; ++k) Ht[k] = static_cast<T>(solid ? Hp[k] : src * (2.0 * H[k] - Hp[k]));
     }
     if (real) {
       double* __restrict__ w0 = hist;
@@ -973,8 +990,9 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
       stb_nt(w0 + 4 * NC, cd, F.n);
     }
 
-    const T tinv = static_cast<T>(inv1p);
-    const T kinv = static_cast<T>(kappa_d * inv1p);
+    // obstacle lanes keep only the equilibrium term (exact: 0 * finite + y)
+    const T tinv = static_cast<T>(solid ? 0.0 : inv1p);
+    const T kinv = static_cast<T>(solid ? 0.0 : kappa_d * inv1p);
     const T wp[3] = {static_cast<T>(P.wp0), static_cast<T>(P.wp1), static_cast<T>(P.wp2)};
 
     // 4-5: limited streaming, bulk term (f only, lambda_0 = 0) and implicit
@@ -1048,13 +1066,20 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
   }
 }
 
+// Storage index x + px (y + py z) of dense cell l = x + nx (y + ny z).
+__device__ __forceinline__ long long store_index(const StepParams& P, long long l) {
+  if (P.px == P.nx && P.py == P.ny) return l;
+  const long long row = l / P.nx, z = row / P.ny;
+  return (row - z * P.ny + z * P.py) * P.px + (l - row * P.nx);
+}
+
 // f := f^eq(fields), h := h^eq(fields) from the fields held in hist; without
 // density the lattice equilibrium density (eps/3)^(3/4) is written to hist.
 template <typename T, bool WH>
 __global__ __launch_bounds__(kBlock) void k_init(const StepParams P) {
   const long long r = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
   if (r >= P.range) return;
-  const long long c = P.cell0 + r;
+  const long long c = store_index(P, P.cell0 + r);
   const long long NC = P.ncell, S = P.pstride;
   T* __restrict__ f = static_cast<T*>(P.f_out);
   T* __restrict__ h = static_cast<T*>(P.h_out);
@@ -1102,7 +1127,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(const StepParams P, double* 
                                                      unsigned long long* bad) {
   const long long r = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
   if (r >= P.range) return;
-  const long long c = P.cell0 + r;
+  const long long c = store_index(P, P.cell0 + r);
   const long long NC = P.range, S = P.pstride;
   const T* __restrict__ f = static_cast<const T*>(P.f_in);
   const T* __restrict__ h = static_cast<const T*>(P.h_in);
@@ -1120,15 +1145,16 @@ __global__ __launch_bounds__(kBlock) void k_moments(const StepParams P, double* 
   out[4 * NC + r] = ok ? F.n : NAN;
 }
 
-// Deterministic domain sums of T^{00}, T^{0a}, N^0: per-block tree sums into
-// partial[block][5], then one block adds the partials in index order.
+// Deterministic domain sums of T^{00}, T^{0a}, N^0 over the P.range dense
+// cells: per-block tree sums into partial[block][5], then one block adds the
+// partials in index order.
 template <typename T, bool WH>
 __global__ __launch_bounds__(kBlock) void k_sums_partial(const StepParams P, double* partial) {
   __shared__ double red[5][kBlock];
-  const long long c = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  const long long l = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
   double v[5] = {0, 0, 0, 0, 0};
-  if (c < P.ncell) {
-    const long long S = P.pstride;
+  if (l < P.range) {
+    const long long S = P.pstride, c = store_index(P, l);
     const T* __restrict__ f = static_cast<const T*>(P.f_in);
     const T* __restrict__ h = static_cast<const T*>(P.h_in);
     moments64<T, WH>(P, [&](auto I) { return f[I * S + c]; }, [&](auto I) { return h[I * S + c]; },

@@ -559,6 +559,8 @@ rlb_status rlb_server_create(const rlb_config* common, uint64_t budget_bytes, in
   s->base.pstride = s->pstride;
   s->base.nx = static_cast<int>(std::min<long long>(cap, 1 << 30));
   s->base.ny = s->base.nz = 1;
+  s->base.px = s->base.nx;
+  s->base.py = 1;
   s->base.hist = s->hist;
   s->base.obst = nullptr;
   s->base.segs = s->d_segs;

@@ -89,3 +89,24 @@ def test_grid_limit_keeps_byte_offsets_in_range():
         assert rlb.rlb_footprint_bytes(big) == 0
         big3 = rlb.config_from(1024, 1024, 257, precision=prec)
         assert rlb.rlb_footprint_bytes(big3) == 0
+
+
+def test_grid_limit_counts_padded_rows():
+    """2D/3D grids are stored with nx padded to a multiple of 64 and ny to a
+    multiple of 4; the limit applies to the stored count, and the footprint
+    includes the pad."""
+    from paper_1302_1125_amd import rlb
+    if not os.path.exists(rlb.LIB_PATH):
+        pytest.skip("librlb.so not built")
+    rlb.load()
+    limit = (1 << 28) - 128
+    per = [rlb.RLB_BC_PERIODIC] * 6
+    ny = limit // 128 + 4  # 65 * ny fits, 128 * ny does not
+    assert 65 * ny <= limit < 128 * ny
+    assert rlb.rlb_footprint_bytes(rlb.config_from(65, ny, 1, precision=rlb.RLB_MIXED, bc=per)) == 0
+    assert rlb.rlb_footprint_bytes(rlb.config_from(64, ny, 1, precision=rlb.RLB_MIXED, bc=per)) > 0
+    a = rlb.rlb_footprint_bytes(rlb.config_from(64, 64, 1, bc=per))
+    b = rlb.rlb_footprint_bytes(rlb.config_from(65, 64, 1, bc=per))
+    c = rlb.rlb_footprint_bytes(rlb.config_from(64, 61, 1, bc=per))
+    assert b > 1.9 * a  # 65-cell rows take 128 cells
+    assert c == a       # 61 rows take 64
