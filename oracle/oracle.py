@@ -44,6 +44,7 @@ class _Cfg(ctypes.Structure):
         ("alpha", ctypes.c_double), ("with_h", ctypes.c_int),
         ("bc", ctypes.c_int * 6), ("face", (ctypes.c_double * 5) * 6),
         ("guard_umax", ctypes.c_double), ("guard_efloor", ctypes.c_double),
+        ("basic", ctypes.c_int),
     ]
 
 
@@ -55,10 +56,10 @@ def _load():
         build(force=True)
     L = ctypes.CDLL(_LIB_PATH)
     dp = ctypes.POINTER(ctypes.c_double)
-    L.orc_lattice.argtypes = [ctypes.c_double, ctypes.POINTER(ctypes.c_int), dp, dp, dp]
-    L.orc_feq.argtypes = [ctypes.c_double] * 5 + [dp]
-    L.orc_heq.argtypes = [ctypes.c_double] * 5 + [dp]
-    L.orc_moments.argtypes = [ctypes.c_double, dp, dp, dp, dp]
+    L.orc_lattice.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp, dp, dp]
+    L.orc_feq.argtypes = [ctypes.c_double, ctypes.c_int] + [ctypes.c_double] * 4 + [dp]
+    L.orc_heq.argtypes = [ctypes.c_double, ctypes.c_int] + [ctypes.c_double] * 4 + [dp]
+    L.orc_moments.argtypes = [ctypes.c_double, ctypes.c_int, dp, dp, dp, dp]
     L.orc_recover.argtypes = [ctypes.c_double] * 5 + [ctypes.c_int, dp]
     L.orc_recover.restype = ctypes.c_int
     L.orc_create.argtypes = [ctypes.POINTER(_Cfg)]
@@ -89,35 +90,36 @@ def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
 
-def lattice(nu: float):
-    """(e[19,3] int, xi[19,4], w[19], w'[19]) in the oracle's own order."""
+def lattice(nu: float, basic: bool = False):
+    """(e[19,3] int, xi[19,4], w[19], w'[19]) in the oracle's own order; the
+    extended set (Sec. II.A) or, with basic=True, the basic set (Sec. II)."""
     L = _load()
     e = np.zeros((Q, 3), dtype=np.int32)
     xi = np.zeros((Q, 4))
     w = np.zeros(Q)
     wp = np.zeros(Q)
-    L.orc_lattice(nu, e.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _p(xi), _p(w), _p(wp))
+    L.orc_lattice(nu, int(basic), e.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _p(xi), _p(w), _p(wp))
     return e.astype(np.int64), xi, w, wp
 
 
-def feq(nu, eps, ux, uy, uz) -> np.ndarray:
+def feq(nu, eps, ux, uy, uz, basic: bool = False) -> np.ndarray:
     out = np.zeros(Q)
-    _load().orc_feq(nu, eps, ux, uy, uz, _p(out))
+    _load().orc_feq(nu, int(basic), eps, ux, uy, uz, _p(out))
     return out
 
 
-def heq(nu, n, ux, uy, uz) -> np.ndarray:
+def heq(nu, n, ux, uy, uz, basic: bool = False) -> np.ndarray:
     out = np.zeros(Q)
-    _load().orc_heq(nu, n, ux, uy, uz, _p(out))
+    _load().orc_heq(nu, int(basic), n, ux, uy, uz, _p(out))
     return out
 
 
-def moments(nu, f, h=None):
+def moments(nu, f, h=None, basic: bool = False):
     f = _f64(f)
     h = None if h is None else _f64(h)
     T0 = np.zeros(4)
     N0 = np.zeros(1)
-    _load().orc_moments(nu, _p(f), _p(h), _p(T0), _p(N0))
+    _load().orc_moments(nu, int(basic), _p(f), _p(h), _p(T0), _p(N0))
     return T0, float(N0[0])
 
 
@@ -145,6 +147,7 @@ class Config:
     face: Sequence[Sequence[float]] = field(default_factory=lambda: [[3.0, 0, 0, 0, 1.0]] * 6)
     guard_umax: float = 0.0
     guard_efloor: float = 1e-10
+    basic: bool = False  # the basic model of Sec. II (dt, euler, alpha, guard unused/off)
 
     def _c(self) -> _Cfg:
         c = _Cfg()
@@ -159,6 +162,7 @@ class Config:
             for j in range(5):
                 c.face[k][j] = float(self.face[k][j])
         c.guard_umax, c.guard_efloor = self.guard_umax, self.guard_efloor
+        c.basic = int(self.basic)
         return c
 
 

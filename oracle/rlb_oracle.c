@@ -29,6 +29,11 @@
  *   - Euler mode: equilibrium of the post-streaming moments;
  *   - admissibility guard (optional, off by default): continuous projection
  *     of the energy-momentum moments into the cone |T^{0a}| <= m_max T^{00}.
+ *   - basic model (Sec. II): energy-momentum distribution f only (the paper
+ *     introduces the density distribution h and its weights with the
+ *     extended set); ghost edges needed by the diagonal links are filled axis
+ *     by axis (x, then y over the x ghosts, then z), so a later axis's FIXED
+ *     face wins at an edge.
  * Parity unpinned: the viscosity calibration of Eq. (41) in the extended
  * scheme (the paper's comparison data are not available).
  */
@@ -43,8 +48,9 @@
 
 typedef struct {
   double nu;
+  int basic;     /* 0: extended set, 1: basic set      */
   double r;      /* c_t / c_0 = sqrt(27)/nu, Eq. (46) */
-  double ca;     /* c_a = sqrt(13)/nu, Eq. (46)       */
+  double ca;     /* c_a = sqrt(13)/nu (extended, Eq. (46)) or sqrt(19)/nu (basic) */
   double c0;     /* c_0 = (3/8)(9 - 2 sqrt 3), Eq. (46) */
   int e[ORC_Q][3];
   double xi[ORC_Q][4];
@@ -54,13 +60,20 @@ typedef struct {
 
 /* Extended D3Q19 set, Eq. (42): rest, c_a(+-1,0,0)_FS, 2 c_a(+-1,+-1,0)_FS;
    4-velocities xi_i = (c_t/c_0, c_a e_i) (Sec. II, after Eq. (30));
-   weights Eqs. (43)-(45); density weights Eqs. (59)-(60). */
-static void make_lattice(double nu, lattice_t* L) {
+   weights Eqs. (43)-(45); density weights Eqs. (59)-(60).
+   Basic set (Sec. II, the D3Q19 configuration and its quadrature):
+   rest, c_a(+-1,0,0)_FS, c_a(+-1,+-1,0)_FS with c_a = sqrt(19)/nu and the
+   same c_t/c_0 and c_0; weights w_0 = 1 + 4 c_t^2 nu^2/(361 c_0^2)
+   - c_t^2/(c_a^2 c_0^2), w_1..6 = c_t^2 (361 - 8 c_a^2 nu^2)/(2166 c_0^2 c_a^2),
+   w_7..18 = c_t^2 nu^2/(1083 c_0^2); no density weights (f only). */
+static void make_lattice(double nu, int basic, lattice_t* L) {
   memset(L, 0, sizeof(*L));
   L->nu = nu;
+  L->basic = basic;
   L->r = sqrt(27.0) / nu;
-  L->ca = sqrt(13.0) / nu;
+  L->ca = (basic ? sqrt(19.0) : sqrt(13.0)) / nu;
   L->c0 = 3.0 / 8.0 * (9.0 - 2.0 * sqrt(3.0));
+  const int d = basic ? 1 : 2; /* length factor of the diagonal links */
   int k = 1; /* e_0 = 0 */
   for (int a = 0; a < 3; ++a)
     for (int s = 1; s >= -1; s -= 2) {
@@ -71,30 +84,38 @@ static void make_lattice(double nu, lattice_t* L) {
     for (int b = a + 1; b < 3; ++b)
       for (int sa = 1; sa >= -1; sa -= 2)
         for (int sb = 1; sb >= -1; sb -= 2) {
-          L->e[k][a] = 2 * sa;
-          L->e[k][b] = 2 * sb;
+          L->e[k][a] = d * sa;
+          L->e[k][b] = d * sb;
           ++k;
         }
   const double r2 = L->r * L->r, ca2 = L->ca * L->ca, nu2 = nu * nu;
-  const double w0 = 1.0 + 7.0 * r2 * nu2 / 676.0 - r2 / ca2;
-  const double w1 = r2 / (1014.0 * ca2) * (169.0 - 2.0 * ca2 * nu2);
-  const double w2 = r2 * nu2 / 8112.0;
-  const double wp0 = 1.0 / 10.0;
-  const double wp1 = 6.0 / 35.0 - 1.0 / (42.0 * ca2);
-  const double wp2 = 1.0 / (84.0 * ca2) - 3.0 / 280.0;
+  double w0, w1, w2, wp0, wp1, wp2;
+  if (basic) {
+    w0 = 1.0 + 4.0 * r2 * nu2 / 361.0 - r2 / ca2;
+    w1 = r2 / (2166.0 * ca2) * (361.0 - 8.0 * ca2 * nu2);
+    w2 = r2 * nu2 / 1083.0;
+    wp0 = wp1 = wp2 = NAN; /* no density distribution in the basic model */
+  } else {
+    w0 = 1.0 + 7.0 * r2 * nu2 / 676.0 - r2 / ca2;
+    w1 = r2 / (1014.0 * ca2) * (169.0 - 2.0 * ca2 * nu2);
+    w2 = r2 * nu2 / 8112.0;
+    wp0 = 1.0 / 10.0;
+    wp1 = 6.0 / 35.0 - 1.0 / (42.0 * ca2);
+    wp2 = 1.0 / (84.0 * ca2) - 3.0 / 280.0;
+  }
   for (int i = 0; i < ORC_Q; ++i) {
-    const int n2 = L->e[i][0] * L->e[i][0] + L->e[i][1] * L->e[i][1] +
-                   L->e[i][2] * L->e[i][2];
+    const int zeros = (L->e[i][0] == 0) + (L->e[i][1] == 0) + (L->e[i][2] == 0);
     L->xi[i][0] = L->r;
     for (int a = 0; a < 3; ++a) L->xi[i][1 + a] = L->ca * L->e[i][a];
-    L->w[i] = (n2 == 0) ? w0 : (n2 == 1) ? w1 : w2;
-    L->wp[i] = (n2 == 0) ? wp0 : (n2 == 1) ? wp1 : wp2;
+    /* rest (3 zero components), axis links (2), diagonal links (1) */
+    L->w[i] = (zeros == 3) ? w0 : (zeros == 2) ? w1 : w2;
+    L->wp[i] = (zeros == 3) ? wp0 : (zeros == 2) ? wp1 : wp2;
   }
 }
 
-void orc_lattice(double nu, int* e, double* xi, double* w, double* wp) {
+void orc_lattice(double nu, int basic, int* e, double* xi, double* w, double* wp) {
   lattice_t L;
-  make_lattice(nu, &L);
+  make_lattice(nu, basic, &L);
   for (int i = 0; i < ORC_Q; ++i) {
     for (int a = 0; a < 3; ++a) e[3 * i + a] = L.e[i][a];
     for (int a = 0; a < 4; ++a) xi[4 * i + a] = L.xi[i][a];
@@ -156,17 +177,17 @@ static void heq_L(const lattice_t* L, double n, double ux, double uy,
   }
 }
 
-void orc_feq(double nu, double eps, double ux, double uy, double uz,
+void orc_feq(double nu, int basic, double eps, double ux, double uy, double uz,
              double* feq) {
   lattice_t L;
-  make_lattice(nu, &L);
+  make_lattice(nu, basic, &L);
   feq_L(&L, eps, ux, uy, uz, feq);
 }
 
-void orc_heq(double nu, double n, double ux, double uy, double uz,
+void orc_heq(double nu, int basic, double n, double ux, double uy, double uz,
              double* heq) {
   lattice_t L;
-  make_lattice(nu, &L);
+  make_lattice(nu, basic, &L);
   heq_L(&L, n, ux, uy, uz, heq);
 }
 
@@ -184,10 +205,10 @@ static void moments_L(const lattice_t* L, const double* f, long fs,
   *N0 = n0;
 }
 
-void orc_moments(double nu, const double* f, const double* h, double* T0,
+void orc_moments(double nu, int basic, const double* f, const double* h, double* T0,
                  double* N0) {
   lattice_t L;
-  make_lattice(nu, &L);
+  make_lattice(nu, basic, &L);
   moments_L(&L, f, 1, h, 1, T0, N0);
 }
 
@@ -281,9 +302,11 @@ orc_state* orc_create(const orc_config* cfg) {
     if (n[a] == 1 && (lo == ORC_BC_FIXED || hi == ORC_BC_FIXED)) return NULL;
     if (n[a] == 1 && lo != ORC_BC_PERIODIC) return NULL;
   }
+  if (cfg->basic && (cfg->euler || cfg->alpha != 0.0 || cfg->guard_umax > 0 || cfg->with_h))
+    return NULL;
   orc_state* S = (orc_state*)calloc(1, sizeof(orc_state));
   S->cfg = *cfg;
-  make_lattice(cfg->nu, &S->L);
+  make_lattice(cfg->nu, cfg->basic, &S->L);
   S->ncell = 1;
   S->npad = 1;
   for (int a = 0; a < 3; ++a) {
@@ -296,11 +319,11 @@ orc_state* orc_create(const orc_config* cfg) {
   const long P = ORC_Q * S->npad;
   S->f = alloc_nan(P);
   S->fn = alloc_nan(P);
-  S->fs = cfg->euler ? alloc_nan(P) : NULL;
+  S->fs = (cfg->euler || cfg->basic) ? alloc_nan(P) : NULL;
   if (cfg->with_h) {
     S->h = alloc_nan(P);
     S->hn = alloc_nan(P);
-    S->hs = cfg->euler ? alloc_nan(P) : NULL;
+    S->hs = (cfg->euler || cfg->basic) ? alloc_nan(P) : NULL;
   }
   S->fields = alloc_nan(5 * S->ncell);
   S->hist = alloc_nan(5 * S->ncell);
@@ -519,7 +542,106 @@ static int guard_project(const orc_state* S, const double* T0, double N0,
   return (th < 1.0 || thh < 1.0) ? 1 : 0;
 }
 
+/* Ghost layers of the basic model, whose diagonal links also read the edge
+   ghosts: the axes are filled in turn (x, then y over the filled x range,
+   then z over the filled x and y ranges), each by its own boundary
+   condition as in fill_ghosts, so at an edge a later axis's FIXED face wins
+   and otherwise the earlier axis's value is carried along. */
+static void fill_ghosts_edges(orc_state* S, double* arr, const double face[6][ORC_Q]) {
+  for (int a = 0; a < 3; ++a) {
+    if (S->n[a] == 1) continue;
+    int lo[3], hi[3];
+    for (int b = 0; b < 3; ++b) {
+      lo[b] = (b < a) ? -S->pad[b] : 0;
+      hi[b] = (b < a) ? S->n[b] + S->pad[b] : S->n[b];
+    }
+    for (int g = 1; g <= 2; ++g)
+      for (int side = 0; side < 2; ++side) {
+        const int bc = S->cfg.bc[2 * a + side];
+        const int ghost = side ? S->n[a] - 1 + g : -g;
+        const int src = (bc == ORC_BC_PERIODIC) ? (side ? g - 1 : S->n[a] - g)
+                                                : (side ? S->n[a] - 1 : 0);
+        const int b = (a + 1) % 3, d = (a + 2) % 3;
+        for (int jb = lo[b]; jb < hi[b]; ++jb)
+          for (int jd = lo[d]; jd < hi[d]; ++jd) {
+            int cg[3], cs[3];
+            cg[a] = ghost; cg[b] = jb; cg[d] = jd;
+            cs[a] = src; cs[b] = jb; cs[d] = jd;
+            const long pg = pidx(S, cg[0], cg[1], cg[2]);
+            const long ps = pidx(S, cs[0], cs[1], cs[2]);
+            for (int i = 0; i < ORC_Q; ++i)
+              arr[i * S->npad + pg] = (bc == ORC_BC_FIXED)
+                                          ? face[2 * a + side][i]
+                                          : arr[i * S->npad + ps];
+          }
+      }
+  }
+}
+
+/* One step of the basic model (Sec. II):
+ *   f_i(x + c_a (c_0/c_t) dt e_i, t + dt) - f_i(x, t)
+ *       = -(c_0 nu dt / (tau c_t)) (f_i - f_i^eq),
+ * with dt = c_t dx / (c_a c_0), so each population moves exactly one link
+ * e_i per step; no bulk term, no limiter, no density distribution.  The
+ * collision is applied at every cell, the post-collision values are copied
+ * into the ghost layers, and every population is then pulled from x - e_i. */
+static int64_t step_basic(orc_state* S, int64_t nsteps) {
+  const lattice_t* L = &S->L;
+  const long NC = S->ncell, NP = S->npad;
+  const double dt = L->r / L->ca;           /* c_t dx / (c_a c_0), dx = 1 */
+  const double omega_tau = L->nu * dt / L->r; /* c_0 nu dt / c_t */
+  for (int64_t it = 0; it < nsteps; ++it) {
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (long c = 0; c < NC; ++c) {
+      const int x = (int)(c % S->n[0]);
+      const int y = (int)((c / S->n[0]) % S->n[1]);
+      const int z = (int)(c / ((long)S->n[0] * S->n[1]));
+      const long p = pidx(S, x, y, z);
+      double fl[5], fe[ORC_Q];
+      if (S->obst && S->obst[c]) {
+        /* held at the equilibrium of its prescribed state */
+        fields_at(S->obst_fields, NC, c, fl);
+        feq_L(L, fl[0], fl[1], fl[2], fl[3], fe);
+        for (int i = 0; i < ORC_Q; ++i) S->fs[i * NP + p] = fe[i];
+        continue;
+      }
+      double T0[4], N0;
+      moments_L(L, S->f + p, NP, NULL, NP, T0, &N0);
+      if (orc_recover(T0[0], T0[1], T0[2], T0[3], N0, 0, fl) != 0) {
+        bad = 1;
+        continue;
+      }
+      const double omega = omega_tau / tau_of(S, fl);
+      feq_L(L, fl[0], fl[1], fl[2], fl[3], fe);
+      for (int i = 0; i < ORC_Q; ++i) {
+        const double fi = S->f[i * NP + p];
+        S->fs[i * NP + p] = fi - omega * (fi - fe[i]);
+      }
+    }
+    if (bad) return 1 + S->step;
+    fill_ghosts_edges(S, S->fs, (const double(*)[ORC_Q])S->face_f);
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < NC; ++c) {
+      const int x = (int)(c % S->n[0]);
+      const int y = (int)((c / S->n[0]) % S->n[1]);
+      const int z = (int)(c / ((long)S->n[0] * S->n[1]));
+      const long p = pidx(S, x, y, z);
+      for (int i = 0; i < ORC_Q; ++i) {
+        const long q = pidx(S, x - L->e[i][0], y - L->e[i][1], z - L->e[i][2]);
+        S->fn[i * NP + p] = S->fs[i * NP + q];
+      }
+      if (S->obst && S->obst[c])
+        for (int i = 0; i < ORC_Q; ++i) S->fn[i * NP + p] = S->fs[i * NP + p];
+    }
+    double* t = S->f; S->f = S->fn; S->fn = t;
+    S->step += 1;
+  }
+  return 0;
+}
+
 int64_t orc_step(orc_state* S, int64_t nsteps) {
+  if (S->cfg.basic) return step_basic(S, nsteps);
   const lattice_t* L = &S->L;
   const long NC = S->ncell, NP = S->npad;
   const int with_h = S->cfg.with_h;

@@ -39,22 +39,27 @@ typedef struct {
   double face[6][5];  /* (eps,ux,uy,uz,n) of FIXED faces                        */
   double guard_umax;  /* admissibility guard; 0 = off                           */
   double guard_efloor;/* energy floor used by the guard                        */
+  int basic;          /* 1: the basic model of Sec. II (standard D3Q19, exact
+                         streaming with dt = c_t dx/(c_a c_0), explicit Marle
+                         collision, no bulk term, no limiter, f only); euler,
+                         alpha, with_h and the guard must be off; dt unused   */
 } orc_config;
 
 typedef struct orc_state orc_state;
 
-/* Lattice: velocity e_i (integer, 3 per pop), 4-vector xi_i = (c_t/c_0, c_a e_i),
-   weights w_i of Eqs. (43)-(45) and w'_i of Eqs. (59)-(60). */
-void orc_lattice(double nu, int* e /*19x3*/, double* xi /*19x4*/,
+/* Lattice (basic = 0: the extended set of Sec. II.A, Eq. (42); basic = 1: the
+   basic D3Q19 set of Sec. II): velocity e_i (integer, 3 per pop), 4-vector
+   xi_i = (c_t/c_0, c_a e_i), weights w_i and density weights w'_i. */
+void orc_lattice(double nu, int basic, int* e /*19x3*/, double* xi /*19x4*/,
                  double* w /*19*/, double* wp /*19*/);
 
 /* Discrete equilibria (reading M of Eq. (29) fixed by Eq. (36)) and Eq. (58). */
-void orc_feq(double nu, double eps, double ux, double uy, double uz, double* feq);
-void orc_heq(double nu, double n, double ux, double uy, double uz, double* heq);
+void orc_feq(double nu, int basic, double eps, double ux, double uy, double uz, double* feq);
+void orc_heq(double nu, int basic, double n, double ux, double uy, double uz, double* heq);
 
 /* Moments T^{00}, T^{0a} of f and N^0 of h; fields (eps,ux,uy,uz,n) from them.
    Returns 0 if admissible, -1 if not (fields then hold NaN). */
-void orc_moments(double nu, const double* f, const double* h /*nullable*/,
+void orc_moments(double nu, int basic, const double* f, const double* h /*nullable*/,
                  double* T0 /*4: T^00,T^0x,T^0y,T^0z*/, double* N0);
 int orc_recover(double T00, double T0x, double T0y, double T0z, double N0,
                 int with_h, double* fields /*5*/);
