@@ -156,7 +156,7 @@ def cpu_baseline(workload: str, precision: int, budget_s: float):
     cfg = O.Config(nx=w.nx, ny=w.ny, nz=w.nz, nu=w.nu, dt=w.dt, euler=(w.collision == 1),
                    tau_mode=w.tau_mode, tau=w.tau, eta_over_s=w.eta_over_s, alpha=w.alpha,
                    with_h=bool(w.with_density), bc=w.bc, face=w.face_states,
-                   guard_umax=w.guard_umax, guard_efloor=w.guard_efloor)
+                   guard_umax=w.guard_umax, guard_efloor=w.guard_efloor, basic=(w.lattice == 1))
     o = O.Oracle(cfg)
     o.init(w.eps, w.ux, w.uy, w.uz, w.n if w.with_density else None, w.obstacle)
     t0 = time.perf_counter()

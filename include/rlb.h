@@ -58,6 +58,7 @@ enum { RLB_FP64 = 0, RLB_MIXED = 1 };              /* storage/arith precision */
 enum { RLB_COLL_IMPLICIT = 0, RLB_COLL_EULER = 1 }; /* Eq. (57) | Sec. III     */
 enum { RLB_TAU_UNIFORM = 0, RLB_TAU_ETA_OVER_S = 1 };
 enum { RLB_BC_PERIODIC = 0, RLB_BC_FIXED = 1, RLB_BC_OUTFLOW = 2 };
+enum { RLB_LATTICE_EXTENDED = 0, RLB_LATTICE_BASIC = 1 };  /* Sec. II.A | Sec. II */
 
 /* Run configuration.  Lattice units: delta x = 1. */
 typedef struct {
@@ -99,6 +100,19 @@ typedef struct {
                            m_1 = m(1 - 2(1 - guard_umax)).  Not in the
                            paper; it is silent on inadmissible states.      */
   double guard_efloor;  /* floor of T^{00} and n used by the guard; > 0     */
+  int32_t lattice;      /* RLB_LATTICE_EXTENDED (default): the extended
+                           model above.  RLB_LATTICE_BASIC: the basic model
+                           of Sec. II -- standard D3Q19 set (diagonal links
+                           (+-1,+-1,0), c_a = sqrt(19)/nu), exact streaming
+                           with dt = c_t dx/(c_a c_0) = sqrt(27/19) dx (so
+                           dt_over_dx is ignored), explicit Marle collision
+                           f' = f - omega (f - f^eq), omega = nu^2/(sqrt(19)
+                           tau), no limiter, no bulk term.  Requires
+                           collision = RLB_COLL_IMPLICIT (the regular
+                           collision), with_density = 0 (the paper gives the
+                           density distribution for the extended set only),
+                           alpha = 0 and guard_umax = 0.  The explicit
+                           collision is stable only for omega < 2.          */
 } rlb_config;
 
 typedef struct {
@@ -114,7 +128,7 @@ typedef struct {
 
 /* Fill *cfg with defaults: 64x1x1, FP64, implicit, uniform tau = 1,
    nu = 27^(1/4), dt = 0.25, alpha = 0, no density, periodic, guard off,
-   guard_efloor = 1e-10. */
+   guard_efloor = 1e-10, extended lattice. */
 rlb_status rlb_config_default(rlb_config* cfg);
 
 /* Validate cfg, allocate device memory on the current HIP device and
@@ -227,7 +241,8 @@ typedef struct {
    eta_over_s and alpha are per request).  budget_bytes: device memory of the
    arena (populations, ping-pong, previous fields; at most 2^28 - 128 cells
    are used); chunk_steps: steps per
-   graph launch, even, >= 2.  The server runs on a stream it creates. */
+   graph launch, even, >= 2.  The server runs on a stream it creates.
+   The extended lattice only (RLB_E_INVALID_ARG for RLB_LATTICE_BASIC). */
 rlb_status rlb_server_create(const rlb_config* common, uint64_t budget_bytes, int32_t chunk_steps,
                              rlb_server** out);
 

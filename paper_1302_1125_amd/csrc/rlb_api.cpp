@@ -80,7 +80,15 @@ rlb_status validate(const rlb_config* c) {
   if (c->tau_mode != RLB_TAU_UNIFORM && c->tau_mode != RLB_TAU_ETA_OVER_S)
     return fail(RLB_E_INVALID_ARG, "tau_mode");
   if (!(c->nu > 0 && std::isfinite(c->nu))) return fail(RLB_E_INVALID_ARG, "nu must be > 0");
-  if (!(c->dt_over_dx > 0 && c->dt_over_dx <= 0.5)) return fail(RLB_E_INVALID_ARG, "dt_over_dx in (0, 0.5]");
+  if (c->lattice != RLB_LATTICE_EXTENDED && c->lattice != RLB_LATTICE_BASIC)
+    return fail(RLB_E_INVALID_ARG, "lattice");
+  if (c->lattice == RLB_LATTICE_BASIC) {
+    if (c->collision != RLB_COLL_IMPLICIT || c->with_density || c->alpha != 0.0 || c->guard_umax != 0.0)
+      return fail(RLB_E_INVALID_ARG,
+                  "basic lattice: regular collision only, no density, alpha = 0, guard off");
+  } else if (!(c->dt_over_dx > 0 && c->dt_over_dx <= 0.5)) {
+    return fail(RLB_E_INVALID_ARG, "dt_over_dx in (0, 0.5]");
+  }
   if (c->tau_mode == RLB_TAU_UNIFORM && !(c->tau > 0 && std::isfinite(c->tau)))
     return fail(RLB_E_INVALID_ARG, "tau must be > 0");
   if (!(c->eta_over_s >= 0 && std::isfinite(c->eta_over_s))) return fail(RLB_E_INVALID_ARG, "eta_over_s >= 0");
@@ -219,19 +227,25 @@ namespace {
 
 void fill_constants(const rlb_config& c, rlb::StepParams& p) {
   const double nu = c.nu;
+  const bool basic = c.lattice == RLB_LATTICE_BASIC;
+  // (c_a nu)^2: 13 for the extended set (Eq. (46)), 19 for the basic set
+  const double ca2nu2 = basic ? 19.0 : 13.0;
+  // basic model: exact streaming fixes dt = c_t dx / (c_a c_0) = sqrt(27/19)
+  const double dt = basic ? std::sqrt(27.0 / 19.0) : c.dt_over_dx;
+  p.lattice = basic ? 1 : 0;
   p.a_scale = nu * nu / 27.0;
   p.r = std::sqrt(27.0) / nu;
-  p.ca = std::sqrt(13.0) / nu;
-  p.ca2 = 13.0 / (nu * nu);
+  p.ca = std::sqrt(ca2nu2) / nu;
+  p.ca2 = ca2nu2 / (nu * nu);
   p.rca = p.r * p.ca;
   p.inv_r = nu / std::sqrt(27.0);
   p.wp0 = 0.1;
   p.wp1 = 6.0 / 35.0 - 1.0 / (42.0 * p.ca2);
   p.wp2 = 1.0 / (84.0 * p.ca2) - 3.0 / 280.0;
-  p.k1 = 4.0 * std::sqrt(13.0 / 27.0);
-  p.omega_c = nu * nu * c.dt_over_dx / std::sqrt(27.0);
+  p.k1 = 4.0 * std::sqrt(ca2nu2 / 27.0);
+  p.omega_c = nu * nu * dt / std::sqrt(27.0);
   p.kappa = p.omega_c * c.alpha;
-  p.dtv = c.dt_over_dx * std::sqrt(13.0 / 27.0);
+  p.dtv = dt * std::sqrt(ca2nu2 / 27.0);
   p.tau = c.tau;
   p.nu2_etas = nu * nu * c.eta_over_s;
   p.tau_mode = c.tau_mode;

@@ -64,6 +64,7 @@ struct StepParams {
   long long pstride;       // elements per population array (population_stride)
   int nx, ny, nz;
   int px, py;              // row pitch, rows per plane (row_pitch, plane_rows)
+  int lattice;             // 0: extended model (Sec. II.A), 1: basic model (Sec. II)
   // Workgroup tiling: tile_x * tile_y == kBlock cells of one z-plane, and a
   // traversal order that keeps stencil reuse inside one XCD's L2.  Tiles are
   // grouped into pencils of pw x ph tiles (pw divides ntx, ph divides nty).

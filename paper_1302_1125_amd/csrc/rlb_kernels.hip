@@ -75,6 +75,19 @@ __host__ __device__ constexpr double weight(int i) {
   return i == 0 ? -539.0 / 676.0 : (i <= 6 ? 99.0 / 338.0 : 9.0 / 2704.0);
 }
 
+// Lattice L = 0: the extended set above; L = 1: the basic D3Q19 set of
+// Sec. II (diagonal links (+-1, +-1, 0), c_a = sqrt(19)/nu), whose weights
+// after the same substitution are -44/361, 99/722 and 9/361.
+template <int L>
+__host__ __device__ constexpr Vel vel_l(int i) {
+  const int d = (L == 1 && i >= 7) ? 2 : 1;
+  return Vel{vel(i).x / d, vel(i).y / d, vel(i).z / d};
+}
+template <int L>
+__host__ __device__ constexpr double weight_l(int i) {
+  return L == 0 ? weight(i) : (i == 0 ? -44.0 / 361.0 : (i <= 6 ? 99.0 / 722.0 : 9.0 / 361.0));
+}
+
 template <int B, int E, typename F>
 __device__ __forceinline__ void static_for(F&& f) {
   if constexpr (B < E) {
@@ -98,9 +111,9 @@ __host__ __device__ constexpr int n_axes() {
 // bracket_i(K) = K0 + sum_a e^a K[1+a] + sum_a (e^a)^2 K[4+a]
 //              + e^x e^y K7 + e^x e^z K8 + e^y e^z K9.
 // ---------------------------------------------------------------------------
-template <int I, typename C>
+template <int I, int L = 0, typename C>
 __device__ __forceinline__ C bracket(const C* K) {
-  constexpr Vel e = vel(I);
+  constexpr Vel e = vel_l<L>(I);
   C s = K[0];
   if constexpr (e.x != 0) s += C(e.x) * K[1] + C(e.x * e.x) * K[4];
   if constexpr (e.y != 0) s += C(e.y) * K[2] + C(e.y * e.y) * K[5];
@@ -114,9 +127,15 @@ __device__ __forceinline__ C bracket(const C* K) {
 // f^eq_i = w_i bracket_i(K) (moment-exact reading of Eq. (29), fixed by
 // Eq. (36) with eps = 3p): A = nu^2 eps / 27, G = A gamma^2,
 // K0 = A - 16/15 G |u|^2, K_a = 4 sqrt(13/27) G u^a, K_aa = 52/15 G (u^a)^2,
-// K_ab = 13 G u^a u^b.
+// K_ab = 13 G u^a u^b.  The basic set has the same moments up to fourth
+// order, so the same polynomial in xi_i = c_a e_i: with (c_a nu)^2 = 19
+// instead of 13, K_a = 4 sqrt(19/27) G u^a (P.k1), K_aa = 76/15 G (u^a)^2,
+// K_ab = 19 G u^a u^b.
+template <int L = 0>
 __device__ __forceinline__ void feq_coeffs(const StepParams& P, double eps, double ux, double uy,
                                            double uz, double g2, double* K) {
+  constexpr double kaa = L == 0 ? 52.0 / 15.0 : 76.0 / 15.0;
+  constexpr double kab = L == 0 ? 13.0 : 19.0;
   const double A = P.a_scale * eps;
   const double G = A * g2;
   const double u2 = ux * ux + uy * uy + uz * uz;
@@ -125,11 +144,11 @@ __device__ __forceinline__ void feq_coeffs(const StepParams& P, double eps, doub
   K[1] = c1 * ux;
   K[2] = c1 * uy;
   K[3] = c1 * uz;
-  const double c2 = (52.0 / 15.0) * G;
+  const double c2 = kaa * G;
   K[4] = c2 * ux * ux;
   K[5] = c2 * uy * uy;
   K[6] = c2 * uz * uz;
-  const double c3 = 13.0 * G;
+  const double c3 = kab * G;
   K[7] = c3 * ux * uy;
   K[8] = c3 * ux * uz;
   K[9] = c3 * uy * uz;
@@ -684,13 +703,13 @@ __device__ __forceinline__ bool guard_eval(const StepParams& P, double E, double
   return th < 1.0 || thh < 1.0;
 }
 
-// FP64 moments of 19 (+19) values in canonical order.
-template <typename T, bool WH, typename LF, typename LH>
+// FP64 moments of 19 (+19) values in canonical order (lattice L).
+template <typename T, bool WH, int L = 0, typename LF, typename LH>
 __device__ __forceinline__ void moments64(const StepParams& P, LF&& fval, LH&& hval, double& E,
                                           double& Mx, double& My, double& Mz, double& N0) {
   double s0 = 0.0, sx = 0.0, sy = 0.0, sz = 0.0, sh = 0.0;
   static_for<0, Q>([&](auto I) {
-    constexpr Vel e = vel(I);
+    constexpr Vel e = vel_l<L>(I);
     const double v = static_cast<double>(fval(I));
     s0 += v;
     if constexpr (e.x != 0) sx += double(e.x) * v;
@@ -1066,6 +1085,89 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Basic model (Sec. II): standard D3Q19 set, exact streaming (dt = c_t dx /
+// (c_a c_0) moves every population one link per step), explicit Marle
+// collision f' = f - omega (f - f^eq), omega = c_0 nu dt / (c_t tau); no
+// limiter, no bulk term, energy-momentum distribution only.  The arrays hold
+// post-collision values: a step pulls f_i from x - e_i, forms the moments,
+// recovers the fields, collides and stores, one thread per cell with global
+// loads (no stencil beyond one link, so no LDS staging).  The pulled cell
+// x - e_i is mapped per axis (periodic wrap, outflow clamp); across a FIXED
+// face it is that face's slot, and at an edge the later axis's FIXED face
+// wins (axis-by-axis ghost filling).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ unsigned pull_offset(const StepParams& P, int x, int y, int z, int ex,
+                                                int ey, int ez) {
+  int q[3] = {x - ex, y - ey, z - ez};
+  const int n[3] = {P.nx, P.ny, P.nz};
+  long long face = -1;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (q[a] >= 0 && q[a] < n[a]) continue;
+    const int side = q[a] < 0 ? 0 : 1;
+    const int b = P.bc[2 * a + side];
+    if (b == kBcFixed) {
+      face = P.ncell + 2 * a + side;
+      q[a] = side ? n[a] - 1 : 0;
+    } else if (b == kBcPeriodic) {
+      q[a] += side ? -n[a] : n[a];
+    } else {
+      q[a] = side ? n[a] - 1 : 0;
+    }
+  }
+  const long long idx =
+      face >= 0 ? face : q[0] + static_cast<long long>(P.px) * (q[1] + static_cast<long long>(P.py) * q[2]);
+  return static_cast<unsigned>(idx) * static_cast<unsigned>(sizeof(T));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_step_basic(const T* __restrict__ fin,
+                                                        T* __restrict__ fout,
+                                                        const double* __restrict__ hist,
+                                                        const uint8_t* __restrict__ obst,
+                                                        const StepParams P) {
+  int x, y, z;
+  if (!cell_of(P, x, y, z)) return;
+  if (x >= P.nx || y >= P.ny) return;  // no barriers: lanes past the end leave
+  const long long S = P.pstride, NC = P.ncell;
+  const long long c = x + static_cast<long long>(P.px) * (y + static_cast<long long>(P.py) * z);
+  const unsigned cb = static_cast<unsigned>(c) * static_cast<unsigned>(sizeof(T));
+  if (obst != nullptr && obst[c] != 0) {
+    // held at the equilibrium of its prescribed fields
+    const double eps = hist[c], ux = hist[NC + c], uy = hist[2 * NC + c], uz = hist[3 * NC + c];
+    const double g2 = 1.0 / (1.0 - (ux * ux + uy * uy + uz * uz));
+    double K[10];
+    feq_coeffs<1>(P, eps, ux, uy, uz, g2, K);
+    static_for<0, Q>([&](auto I) {
+      stb_nt(fout + I * S, cb, static_cast<T>(weight_l<1>(I) * bracket<I, 1>(K)));
+    });
+    return;
+  }
+  T f[Q];
+  static_for<0, Q>([&](auto I) {
+    constexpr Vel e = vel_l<1>(I);
+    f[I] = ldb(fin + I * S, pull_offset<T>(P, x, y, z, e.x, e.y, e.z));
+  });
+  double E, Mx, My, Mz, N0;
+  moments64<T, false, 1>(P, [&](auto I) { return f[I]; }, [&](auto I) { return T(0); }, E, Mx, My,
+                         Mz, N0);
+  Fields F;
+  const bool ok = recover<false>(E, Mx, My, Mz, N0, F);
+  flag_bad(P.bad_step, !ok, P.step_index);
+  const T om = static_cast<T>(P.omega_c / tau_of<T, false>(P, F, P.tau, P.nu2_etas));
+  double K[10];
+  feq_coeffs<1>(P, F.eps, F.ux, F.uy, F.uz, F.g2, K);
+  T Kt[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) Kt[k] = static_cast<T>(K[k]);
+  static_for<0, Q>([&](auto I) {
+    const T feq = static_cast<T>(weight_l<1>(I)) * bracket<I, 1>(Kt);
+    stb_nt(fout + I * S, cb, f[I] - om * (f[I] - feq));
+  });
+}
+
 // Storage index x + px (y + py z) of dense cell l = x + nx (y + ny z).
 __device__ __forceinline__ long long store_index(const StepParams& P, long long l) {
   if (P.px == P.nx && P.py == P.ny) return l;
@@ -1075,7 +1177,8 @@ __device__ __forceinline__ long long store_index(const StepParams& P, long long 
 
 // f := f^eq(fields), h := h^eq(fields) from the fields held in hist; without
 // density the lattice equilibrium density (eps/3)^(3/4) is written to hist.
-template <typename T, bool WH>
+// L: lattice (0 extended, 1 basic).
+template <typename T, bool WH, int L>
 __global__ __launch_bounds__(kBlock) void k_init(const StepParams P) {
   const long long r = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
   if (r >= P.range) return;
@@ -1087,9 +1190,11 @@ __global__ __launch_bounds__(kBlock) void k_init(const StepParams P) {
                uz = P.hist[3 * NC + c];
   const double g2 = 1.0 / (1.0 - (ux * ux + uy * uy + uz * uz));
   double K[10];
-  feq_coeffs(P, eps, ux, uy, uz, g2, K);
-  static_for<0, Q>([&](auto I) { f[I * S + c] = static_cast<T>(weight(I) * bracket<I>(K)); });
+  feq_coeffs<L>(P, eps, ux, uy, uz, g2, K);
+  static_for<0, Q>(
+      [&](auto I) { f[I * S + c] = static_cast<T>(weight_l<L>(I) * bracket<I, L>(K)); });
   if constexpr (WH) {
+    static_assert(L == 0, "the density distribution is carried by the extended model only");
     double H[10];
     heq_coeffs(P, P.hist[4 * NC + c], ux, uy, uz, sqrt(g2), H);
     static_for<0, Q>([&](auto I) { h[I * S + c] = static_cast<T>(wprime<I>(P) * bracket<I>(H)); });
@@ -1099,18 +1204,18 @@ __global__ __launch_bounds__(kBlock) void k_init(const StepParams P) {
 }
 
 // Face slots: equilibria of the six face states in both ping-pong copies.
-template <typename T>
+template <typename T, int L>
 __global__ void k_face_slots(const StepParams P, const double* states, T* f0, T* f1, T* h0, T* h1) {
   const int s = threadIdx.x;
   if (s >= kFaceSlots) return;
   const double* q = states + 5 * s;
   const double g2 = 1.0 / (1.0 - (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]));
   double K[10], H[10];
-  feq_coeffs(P, q[0], q[1], q[2], q[3], g2, K);
+  feq_coeffs<L>(P, q[0], q[1], q[2], q[3], g2, K);
   heq_coeffs(P, q[4], q[1], q[2], q[3], sqrt(g2), H);
   const long long S = P.pstride, at = P.ncell + s;
   static_for<0, Q>([&](auto I) {
-    const T fe = static_cast<T>(weight(I) * bracket<I>(K));
+    const T fe = static_cast<T>(weight_l<L>(I) * bracket<I, L>(K));
     f0[I * S + at] = fe;
     f1[I * S + at] = fe;
     if (h0 != nullptr) {
@@ -1122,7 +1227,7 @@ __global__ void k_face_slots(const StepParams P, const double* states, T* f0, T*
 }
 
 // Fields of the current populations (FP64 recovery); NaN where inadmissible.
-template <typename T, bool WH>
+template <typename T, bool WH, int L>
 __global__ __launch_bounds__(kBlock) void k_moments(const StepParams P, double* out,
                                                      unsigned long long* bad) {
   const long long r = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
@@ -1132,8 +1237,8 @@ __global__ __launch_bounds__(kBlock) void k_moments(const StepParams P, double* 
   const T* __restrict__ f = static_cast<const T*>(P.f_in);
   const T* __restrict__ h = static_cast<const T*>(P.h_in);
   double E, Mx, My, Mz, N0;
-  moments64<T, WH>(P, [&](auto I) { return f[I * S + c]; }, [&](auto I) { return h[I * S + c]; },
-                   E, Mx, My, Mz, N0);
+  moments64<T, WH, L>(P, [&](auto I) { return f[I * S + c]; }, [&](auto I) { return h[I * S + c]; },
+                      E, Mx, My, Mz, N0);
   Fields F;
   const bool ok = recover<WH>(E, Mx, My, Mz, N0, F);
   const bool obst = P.obst != nullptr && P.obst[c] != 0;
@@ -1148,7 +1253,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(const StepParams P, double* 
 // Deterministic domain sums of T^{00}, T^{0a}, N^0 over the P.range dense
 // cells: per-block tree sums into partial[block][5], then one block adds the
 // partials in index order.
-template <typename T, bool WH>
+template <typename T, bool WH, int L>
 __global__ __launch_bounds__(kBlock) void k_sums_partial(const StepParams P, double* partial) {
   __shared__ double red[5][kBlock];
   const long long l = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
@@ -1157,8 +1262,8 @@ __global__ __launch_bounds__(kBlock) void k_sums_partial(const StepParams P, dou
     const long long S = P.pstride, c = store_index(P, l);
     const T* __restrict__ f = static_cast<const T*>(P.f_in);
     const T* __restrict__ h = static_cast<const T*>(P.h_in);
-    moments64<T, WH>(P, [&](auto I) { return f[I * S + c]; }, [&](auto I) { return h[I * S + c]; },
-                     v[0], v[1], v[2], v[3], v[4]);
+    moments64<T, WH, L>(P, [&](auto I) { return f[I * S + c]; }, [&](auto I) { return h[I * S + c]; },
+                        v[0], v[1], v[2], v[3], v[4]);
   }
   for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = v[k];
   __syncthreads();
@@ -1275,57 +1380,96 @@ hipError_t launch_seg_ghosts(const StepParams& p, bool fp64, long long lo, long 
 
 hipError_t launch_step(const StepParams& p, bool fp64, int act_mask, bool with_h, bool euler,
                        hipStream_t s) {
+  if (p.lattice == 1) {
+    // basic model: f only, regular collision (checked by the host)
+    if (with_h || euler) return hipErrorInvalidValue;
+    const dim3 grid(static_cast<unsigned>(p.tiles_per_xcd * kXcds));
+    if (fp64)
+      hipLaunchKernelGGL(k_step_basic<double>, grid, dim3(kBlock), 0, s,
+                         static_cast<const double*>(p.f_in), static_cast<double*>(p.f_out), p.hist,
+                         p.obst, p);
+    else
+      hipLaunchKernelGGL(k_step_basic<float>, grid, dim3(kBlock), 0, s,
+                         static_cast<const float*>(p.f_in), static_cast<float*>(p.f_out), p.hist,
+                         p.obst, p);
+    return hipGetLastError();
+  }
   return fp64 ? launch_step_p<double>(p, act_mask, with_h, euler, s)
               : launch_step_p<float>(p, act_mask, with_h, euler, s);
 }
 
+namespace {
+// Instantiation helpers: (T, with_h, lattice) of the per-cell kernels.  The
+// density distribution exists in the extended model only.
+template <typename T, bool WH, int L>
+void init_t(const StepParams& p, unsigned nb, hipStream_t s) {
+  hipLaunchKernelGGL((k_init<T, WH, L>), dim3(nb), dim3(kBlock), 0, s, p);
+}
+template <typename T>
+void init_p(const StepParams& p, bool with_h, unsigned nb, hipStream_t s) {
+  if (p.lattice == 1) init_t<T, false, 1>(p, nb, s);
+  else if (with_h) init_t<T, true, 0>(p, nb, s);
+  else init_t<T, false, 0>(p, nb, s);
+}
+template <typename T, bool WH, int L>
+void moments_t(const StepParams& p, unsigned nb, double* out, unsigned long long* bad, hipStream_t s) {
+  hipLaunchKernelGGL((k_moments<T, WH, L>), dim3(nb), dim3(kBlock), 0, s, p, out, bad);
+}
+template <typename T>
+void moments_p(const StepParams& p, bool with_h, unsigned nb, double* out, unsigned long long* bad,
+               hipStream_t s) {
+  if (p.lattice == 1) moments_t<T, false, 1>(p, nb, out, bad, s);
+  else if (with_h) moments_t<T, true, 0>(p, nb, out, bad, s);
+  else moments_t<T, false, 0>(p, nb, out, bad, s);
+}
+template <typename T, bool WH, int L>
+void sums_t(const StepParams& p, int nb, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL((k_sums_partial<T, WH, L>), dim3(nb), dim3(kBlock), 0, s, p, partial);
+}
+template <typename T>
+void sums_p(const StepParams& p, bool with_h, int nb, double* partial, hipStream_t s) {
+  if (p.lattice == 1) sums_t<T, false, 1>(p, nb, partial, s);
+  else if (with_h) sums_t<T, true, 0>(p, nb, partial, s);
+  else sums_t<T, false, 0>(p, nb, partial, s);
+}
+template <typename T>
+void face_p(const StepParams& p, const double* states, void* f0, void* f1, void* h0, void* h1,
+            hipStream_t s) {
+  if (p.lattice == 1)
+    hipLaunchKernelGGL((k_face_slots<T, 1>), dim3(1), dim3(64), 0, s, p, states, static_cast<T*>(f0),
+                       static_cast<T*>(f1), static_cast<T*>(h0), static_cast<T*>(h1));
+  else
+    hipLaunchKernelGGL((k_face_slots<T, 0>), dim3(1), dim3(64), 0, s, p, states, static_cast<T*>(f0),
+                       static_cast<T*>(f1), static_cast<T*>(h0), static_cast<T*>(h1));
+}
+}  // namespace
+
 hipError_t launch_init(const StepParams& p, bool fp64, bool with_h, hipStream_t s) {
   const unsigned nb = static_cast<unsigned>((p.range + kBlock - 1) / kBlock);
-  if (fp64) {
-    if (with_h) hipLaunchKernelGGL((k_init<double, true>), dim3(nb), dim3(kBlock), 0, s, p);
-    else hipLaunchKernelGGL((k_init<double, false>), dim3(nb), dim3(kBlock), 0, s, p);
-  } else {
-    if (with_h) hipLaunchKernelGGL((k_init<float, true>), dim3(nb), dim3(kBlock), 0, s, p);
-    else hipLaunchKernelGGL((k_init<float, false>), dim3(nb), dim3(kBlock), 0, s, p);
-  }
+  if (fp64) init_p<double>(p, with_h, nb, s);
+  else init_p<float>(p, with_h, nb, s);
   return hipGetLastError();
 }
 
 hipError_t launch_face_slots(const StepParams& p, bool fp64, const double* states, void* f0, void* f1,
                              void* h0, void* h1, hipStream_t s) {
-  if (fp64)
-    hipLaunchKernelGGL(k_face_slots<double>, dim3(1), dim3(64), 0, s, p, states,
-                       static_cast<double*>(f0), static_cast<double*>(f1), static_cast<double*>(h0),
-                       static_cast<double*>(h1));
-  else
-    hipLaunchKernelGGL(k_face_slots<float>, dim3(1), dim3(64), 0, s, p, states,
-                       static_cast<float*>(f0), static_cast<float*>(f1), static_cast<float*>(h0),
-                       static_cast<float*>(h1));
+  if (fp64) face_p<double>(p, states, f0, f1, h0, h1, s);
+  else face_p<float>(p, states, f0, f1, h0, h1, s);
   return hipGetLastError();
 }
 
 hipError_t launch_moments(const StepParams& p, bool fp64, bool with_h, double* out,
                           unsigned long long* bad, hipStream_t s) {
   const unsigned nb = static_cast<unsigned>((p.range + kBlock - 1) / kBlock);
-  if (fp64) {
-    if (with_h) hipLaunchKernelGGL((k_moments<double, true>), dim3(nb), dim3(kBlock), 0, s, p, out, bad);
-    else hipLaunchKernelGGL((k_moments<double, false>), dim3(nb), dim3(kBlock), 0, s, p, out, bad);
-  } else {
-    if (with_h) hipLaunchKernelGGL((k_moments<float, true>), dim3(nb), dim3(kBlock), 0, s, p, out, bad);
-    else hipLaunchKernelGGL((k_moments<float, false>), dim3(nb), dim3(kBlock), 0, s, p, out, bad);
-  }
+  if (fp64) moments_p<double>(p, with_h, nb, out, bad, s);
+  else moments_p<float>(p, with_h, nb, out, bad, s);
   return hipGetLastError();
 }
 
 hipError_t launch_sums(const StepParams& p, bool fp64, bool with_h, double* partial, int nblocks,
                        double* out5, hipStream_t s) {
-  if (fp64) {
-    if (with_h) hipLaunchKernelGGL((k_sums_partial<double, true>), dim3(nblocks), dim3(kBlock), 0, s, p, partial);
-    else hipLaunchKernelGGL((k_sums_partial<double, false>), dim3(nblocks), dim3(kBlock), 0, s, p, partial);
-  } else {
-    if (with_h) hipLaunchKernelGGL((k_sums_partial<float, true>), dim3(nblocks), dim3(kBlock), 0, s, p, partial);
-    else hipLaunchKernelGGL((k_sums_partial<float, false>), dim3(nblocks), dim3(kBlock), 0, s, p, partial);
-  }
+  if (fp64) sums_p<double>(p, with_h, nblocks, partial, s);
+  else sums_p<float>(p, with_h, nblocks, partial, s);
   hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(kBlock), 0, s, partial, nblocks, out5);
   return hipGetLastError();
 }

@@ -500,6 +500,8 @@ rlb_status rlb_server_create(const rlb_config* common, uint64_t budget_bytes, in
   if (c.tau_mode == RLB_TAU_UNIFORM && !(c.tau > 0)) c.tau = 1.0;
   rlb_status st = rlb_validate_config(&c);
   if (st != RLB_OK) return st;
+  if (c.lattice != RLB_LATTICE_EXTENDED)
+    return rlb_set_error(RLB_E_INVALID_ARG, "the server runs the extended lattice only");
   if (chunk_steps < 2 || chunk_steps % 2 != 0 || chunk_steps > 4096)
     return rlb_set_error(RLB_E_INVALID_ARG, "chunk_steps must be even, 2..4096");
   const uint64_t bpc = bytes_per_cell(c);

@@ -26,6 +26,7 @@ BC_PERIODIC, BC_FIXED, BC_OUTFLOW = 0, 1, 2
 FP64, MIXED = 0, 1
 COLL_IMPLICIT, COLL_EULER = 0, 1
 TAU_UNIFORM, TAU_ETA_OVER_S = 0, 1
+LATTICE_EXTENDED, LATTICE_BASIC = 0, 1
 
 
 @dataclass
@@ -48,6 +49,7 @@ class Workload:
     face_states: List[List[float]] = field(default_factory=lambda: [[3.0, 0.0, 0.0, 0.0, 1.0]] * 6)
     guard_umax: float = 0.0
     guard_efloor: float = 1e-10
+    lattice: int = LATTICE_EXTENDED
     eps: Optional[np.ndarray] = None
     ux: Optional[np.ndarray] = None
     uy: Optional[np.ndarray] = None
@@ -259,6 +261,41 @@ def shock_cloud_3d(nx=200, ny=100, nz=100, regime="weak", viscous=False, steps=N
     w.ux, w.uy, w.uz = _zeros(shape), _zeros(shape), _zeros(shape)
     w.n = n.astype(np.float64)
     w.obstacle = cloud.astype(np.uint8)
+    return w
+
+
+def as_basic(w: Workload, nu=1.0) -> Workload:
+    """The same initial and boundary set-up for the basic model of Sec. II:
+    standard D3Q19, exact streaming, explicit Marle collision, energy-momentum
+    distribution only (no density, no bulk term, no guard; Euler mode does not
+    exist for it, so an inviscid recipe keeps its own relaxation time).
+    nu = 1 by default: the explicit collision needs omega = nu^2/(sqrt(19)
+    tau) < 2, which at nu = 27^(1/4) fails for tau below 0.6 (eta/s = 0.01)."""
+    b = w.copy_with(name=w.name + "_basic", lattice=LATTICE_BASIC, nu=nu, collision=COLL_IMPLICIT,
+                    alpha=0.0, with_density=False, guard_umax=0.0)
+    b.n = None
+    return b
+
+
+def basic_vs_extended_tube(lattice=LATTICE_BASIC, nx=1000, ratio=32.0, eta_over_s=0.01,
+                           precision=FP64) -> Workload:
+    """The paper's comparison of the two models (Sec. III): a 1D tube with
+    pressure ratio 32 (2.495e-7 / 7.785e-9 in its numerical units; the exact
+    plateau moves at beta = 0.64), at rest, eta/s = 0.01, fixed-state ends.
+    Basic model: nu = 1, 300 steps of dt = sqrt(27/19); extended model:
+    nu = 27^(1/4), dt/dx = 0.25, alpha = 0.15, 1400 steps (the same time)."""
+    x = np.arange(nx)
+    shape = (1, 1, nx)
+    eps = np.where(x < nx // 2, 3.0 * ratio, 3.0).astype(np.float64).reshape(shape)
+    basic = lattice == LATTICE_BASIC
+    w = Workload("basic_vs_extended_tube" + ("_basic" if basic else "_extended"), nx, 1, 1,
+                 300 if basic else 1400, precision=precision, tau_mode=TAU_ETA_OVER_S,
+                 eta_over_s=eta_over_s, alpha=0.0 if basic else 0.15, nu=1.0 if basic else NU_DEFAULT,
+                 dt=0.25, bc=[BC_FIXED, BC_FIXED] + [BC_PERIODIC] * 4,
+                 face_states=[[3.0 * ratio, 0.0, 0.0, 0.0, 1.0], [3.0, 0.0, 0.0, 0.0, 1.0]]
+                 + [[3.0, 0.0, 0.0, 0.0, 1.0]] * 4, lattice=lattice)
+    w.eps = eps
+    w.ux, w.uy, w.uz = _zeros(shape), _zeros(shape), _zeros(shape)
     return w
 
 

@@ -10,7 +10,8 @@ def oracle_for(w, **over):
     cfg = O.Config(nx=w.nx, ny=w.ny, nz=w.nz, nu=w.nu, dt=w.dt, euler=(w.collision == 1),
                    tau_mode=w.tau_mode, tau=w.tau, eta_over_s=w.eta_over_s, alpha=w.alpha,
                    with_h=bool(w.with_density), bc=list(w.bc), face=[list(s) for s in w.face_states],
-                   guard_umax=w.guard_umax, guard_efloor=w.guard_efloor)
+                   guard_umax=w.guard_umax, guard_efloor=w.guard_efloor,
+                   basic=(w.lattice == 1))
     for k, v in over.items():
         setattr(cfg, k, v)
     o = O.Oracle(cfg)
@@ -89,7 +90,8 @@ def crop_workload(w, center, radius):
             bc[hi_f] = 2
     sel = np.ix_(idx[0], idx[1], idx[2])
     cw = w.copy_with(nz=len(idx[0]), ny=len(idx[1]), nx=len(idx[2]), bc=bc)
-    cw.eps, cw.ux, cw.uy, cw.uz, cw.n = (a[sel].copy() for a in (w.eps, w.ux, w.uy, w.uz, w.n))
+    cw.eps, cw.ux, cw.uy, cw.uz, cw.n = (None if a is None else a[sel].copy()
+                                         for a in (w.eps, w.ux, w.uy, w.uz, w.n))
     if w.obstacle is not None:
         cw.obstacle = w.obstacle[sel].copy()
     # size-1 axes of the crop must be periodic

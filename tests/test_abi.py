@@ -34,8 +34,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layout_matches_header():
     from paper_1302_1125_amd import rlb
-    # sizeof(rlb_config) in C: 4 + 3*4 + 4*4 + 5*8 + 6*4 + 30*8 + 2*8, padded to 8
-    assert ctypes.sizeof(rlb.rlb_config) == 352
+    # sizeof(rlb_config) in C: 4 + 3*4 + 4*4 + 5*8 + 6*4 + 30*8 + 2*8 + 4, padded to 8
+    assert ctypes.sizeof(rlb.rlb_config) == 360
     assert ctypes.sizeof(rlb.rlb_stats) == 64
     assert ctypes.sizeof(rlb.rlb_request) == 168
     assert ctypes.sizeof(rlb.rlb_server_stats) == 128
@@ -110,3 +110,22 @@ def test_grid_limit_counts_padded_rows():
     c = rlb.rlb_footprint_bytes(rlb.config_from(64, 61, 1, bc=per))
     assert b > 1.9 * a  # 65-cell rows take 128 cells
     assert c == a       # 61 rows take 64
+
+
+def test_basic_lattice_validation():
+    """The basic model (Sec. II) has the regular collision only, no density
+    distribution, no bulk term and no guard; its time step is fixed by exact
+    streaming, so dt_over_dx is not checked for it.  Invalid configurations
+    are rejected before any allocation (footprint 0)."""
+    from paper_1302_1125_amd import rlb
+    if not os.path.exists(rlb.LIB_PATH):
+        pytest.skip("librlb.so not built")
+    rlb.load()
+    per = [rlb.RLB_BC_PERIODIC] * 6
+    ok = rlb.config_from(32, 8, 4, bc=per, lattice=rlb.RLB_LATTICE_BASIC, dt_over_dx=0.0)
+    assert rlb.rlb_footprint_bytes(ok) > 0
+    for bad in (dict(with_density=True), dict(alpha=0.1), dict(guard_umax=0.99),
+                dict(collision=rlb.RLB_COLL_EULER)):
+        cfg = rlb.config_from(32, 8, 4, bc=per, lattice=rlb.RLB_LATTICE_BASIC, **bad)
+        assert rlb.rlb_footprint_bytes(cfg) == 0, bad
+    assert rlb.rlb_footprint_bytes(rlb.config_from(32, 8, 4, bc=per, lattice=2)) == 0

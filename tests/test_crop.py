@@ -30,3 +30,11 @@ def test_crop_shock_cloud_3d():
     w = W.shock_cloud_3d(nx=40, ny=20, nz=20, regime="strong", precision=W.FP64)
     _check(w, [(0, 0, 0), (19, 19, 39), (10, 10, 20), (10, 10, 13), (10, 12, 22), (3, 17, 1),
                (19, 0, 38)], 3)
+
+
+def test_crop_basic_model_3d():
+    # basic model: diagonal links read edge ghosts; inlet, outflow faces, obstacle
+    w = W.as_basic(W.shock_cloud_3d(nx=40, ny=20, nz=20, regime="weak", viscous=True,
+                                    precision=W.FP64))
+    _check(w, [(0, 0, 0), (19, 19, 39), (10, 10, 20), (10, 10, 13), (10, 12, 22), (3, 17, 1),
+               (19, 0, 38)], 3)
