@@ -36,14 +36,16 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes_per_cell(precision: int, with_density: bool, collision: int, obstacle: bool) -> int:
+def algorithmic_bytes_per_cell(precision: int, with_density: bool, collision: int, obstacle: bool,
+                               lattice: int = 0) -> int:
     """Each population read once and written once; previous-step fields read
-    and written once (implicit mode); obstacle mask read once."""
+    and written once (implicit mode of the extended model); obstacle mask
+    read once."""
     e = 8 if precision == 0 else 4
     b = 2 * 19 * e
     if with_density:
         b += 2 * 19 * e
-    if collision == 0:
+    if collision == 0 and lattice == 0:
         b += 2 * 5 * 8
     if obstacle:
         b += 1
@@ -124,7 +126,8 @@ def record_traffic(args):
             d = json.load(f)
     except (OSError, ValueError):
         d = {}
-    d[f"{args.workload}:{args.precision}"] = {
+    name = args.workload + ("_basic" if args.lattice == "basic" else "")
+    d[f"{name}:{args.precision}"] = {
         "kernel_hash": kernel_hash(), "bytes_per_launch": round(fetch + write),
         "fetch_bytes": round(fetch), "write_bytes": round(write),
         "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
@@ -133,10 +136,10 @@ def record_traffic(args):
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(d, f, indent=1, sort_keys=True)
         f.write("\n")
-    print(json.dumps(d[f"{args.workload}:{args.precision}"]))
+    print(json.dumps(d[f"{name}:{args.precision}"]))
 
 
-def cpu_baseline(workload: str, precision: int, budget_s: float):
+def cpu_baseline(workload: str, precision: int, budget_s: float, lattice: str = "extended"):
     """FP64 CPU oracle on a bounded sample of the same workload recipe."""
     from oracle import oracle as O
     from paper_1302_1125_amd import workloads as W
@@ -153,6 +156,9 @@ def cpu_baseline(workload: str, precision: int, budget_s: float):
     else:
         w = make_workload(workload, precision)
         sample = f"{workload} full grid"
+    if lattice == "basic":
+        w = W.as_basic(w)
+        sample += ", basic model"
     cfg = O.Config(nx=w.nx, ny=w.ny, nz=w.nz, nu=w.nu, dt=w.dt, euler=(w.collision == 1),
                    tau_mode=w.tau_mode, tau=w.tau, eta_over_s=w.eta_over_s, alpha=w.alpha,
                    with_h=bool(w.with_density), bc=w.bc, face=w.face_states,
@@ -309,6 +315,8 @@ def main():
                              "shock_cloud_3d_weak", "shock_cloud_3d_strong",
                              "shock_cloud_3d_weak_viscous", "shock_cloud_3d_strong_viscous"])
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--lattice", default="extended", choices=["extended", "basic"],
+                    help="basic: the same recipe run by the basic model of Sec. II (nu = 1)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
@@ -356,6 +364,9 @@ def main():
         return
     precision = rlb.RLB_MIXED if args.precision == "mixed" else rlb.RLB_FP64
     w = make_workload(args.workload, precision)
+    if args.lattice == "basic":
+        from paper_1302_1125_amd import workloads as W
+        w = W.as_basic(w)
     # a dedicated stream (default priority): the library launches on it and
     # the timing events are recorded on it
     stream = torch.cuda.Stream()
@@ -379,7 +390,8 @@ def main():
     kern_ms = ev0.elapsed_time(ev1) / args.steps
     ms_per_step = wall * 1e3 / args.steps
     mlups = w.ncell * args.steps / wall / 1e6
-    bpc = algorithmic_bytes_per_cell(precision, w.with_density, w.collision, w.obstacle is not None)
+    bpc = algorithmic_bytes_per_cell(precision, w.with_density, w.collision, w.obstacle is not None,
+                                     w.lattice)
     bytes_launch = bpc * w.ncell
     achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
     traffic = traffic_entry(w.name, args.precision)
@@ -389,7 +401,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(w.name, precision, args.cpu_seconds)
+        cpu = cpu_baseline(args.workload, precision, args.cpu_seconds, args.lattice)
 
     out = {
         "metric": "cell-updates/s (MLUPS) & % HBM roofline",
@@ -405,7 +417,8 @@ def main():
         "dtype": "f32-storage/f64-recovery" if precision == rlb.RLB_MIXED else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "cells": w.ncell,
-                   "precision": args.precision, "density_distribution": bool(w.with_density),
+                   "precision": args.precision, "lattice": args.lattice,
+                   "density_distribution": bool(w.with_density),
                    "guard_umax": w.guard_umax, "dt_over_dx": w.dt, "nu": w.nu,
                    "eta_over_s": w.eta_over_s, "alpha": w.alpha, "guard_events": stats.guard_events,
                    "bytes_per_cell_update": bpc},
