@@ -419,7 +419,8 @@ def main():
         "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "cells": w.ncell,
                    "precision": args.precision, "lattice": args.lattice,
                    "density_distribution": bool(w.with_density),
-                   "guard_umax": w.guard_umax, "dt_over_dx": w.dt, "nu": w.nu,
+                   "guard_umax": w.guard_umax,
+                   "dt_over_dx": (27.0 / 19.0) ** 0.5 if w.lattice == 1 else w.dt, "nu": w.nu,
                    "eta_over_s": w.eta_over_s, "alpha": w.alpha, "guard_events": stats.guard_events,
                    "bytes_per_cell_update": bpc},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
