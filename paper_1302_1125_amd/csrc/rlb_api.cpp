@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -54,6 +55,7 @@ struct rlb_ctx {
   double* sums_partial = nullptr;
   double* sums_out = nullptr;
   int sums_blocks = 0;
+  int tb_steps = 8;      // 1D: steps per temporally blocked launch (1: one step per launch)
   bool initialised = false;
   bool poisoned = false;
   long long steps = 0;
@@ -352,6 +354,10 @@ rlb_status rlb_create(const rlb_config* cfg, void* hip_stream, rlb_ctx** out) {
   x->py = rlb::plane_rows(cfg->ny);
   x->nstore = static_cast<long long>(x->px) * x->py * cfg->nz;
   x->act_mask = cfg->nz > 1 ? 7 : (cfg->ny > 1 ? 3 : 1);
+  if (const char* e = std::getenv("RLB_TB_STEPS")) {  // tuning override, 1 = off
+    const int v = std::atoi(e);
+    x->tb_steps = v < 1 ? 1 : (v > rlb::kTbMaxSteps ? rlb::kTbMaxSteps : v);
+  }
   if (hip_stream) {
     x->stream = static_cast<hipStream_t>(hip_stream);
   } else {
@@ -482,6 +488,26 @@ rlb_status rlb_step_async(rlb_ctx* x, int64_t nsteps) {
   if (st != RLB_OK) return st;
   const bool wh = x->cfg.with_density != 0;
   const bool eu = x->cfg.collision == RLB_COLL_EULER;
+  if (x->act_mask == 1 && x->cfg.lattice == RLB_LATTICE_EXTENDED && x->tb_steps > 1) {
+    // 1D: temporally blocked launches of up to tb_steps steps each
+    for (int64_t k = 0; k < nsteps;) {
+      const int kb = static_cast<int>(std::min<int64_t>(x->tb_steps, nsteps - k));
+      const int cells = rlb::tb_cells_per_tile(kb);
+      const unsigned grid = static_cast<unsigned>((x->cfg.nx + cells - 1) / cells);
+      rlb::StepParams p = x->base;
+      p.f_in = x->f[x->cur];
+      p.f_out = x->f[1 - x->cur];
+      p.h_in = x->h[x->cur];
+      p.h_out = x->h[1 - x->cur];
+      p.step_index = x->steps;
+      const hipError_t e = rlb::launch_step_tb(p, x->fp64, wh, eu, kb, false, grid, x->stream);
+      if (e != hipSuccess) return hip_fail(e, "step kernel");
+      x->cur = 1 - x->cur;
+      x->steps += kb;
+      k += kb;
+    }
+    return RLB_OK;
+  }
   for (int64_t k = 0; k < nsteps; ++k) {
     rlb::StepParams p = x->base;
     p.f_in = x->f[x->cur];

@@ -137,6 +137,14 @@ hipError_t launch_moments(const StepParams& p, bool fp64, bool with_h, double* o
                           unsigned long long* bad_flag, hipStream_t s);
 hipError_t launch_sums(const StepParams& p, bool fp64, bool with_h, double* partial, int nblocks,
                        double* out5, hipStream_t s);
+// Temporal blocking of 1D domains (extended lattice): kb in [1, kTbMaxSteps]
+// steps per launch; each workgroup owns tb_cells_per_tile(kb) cells.  seg:
+// p.tiles maps the grid onto segments (tiles of that many cells), else the
+// grid covers the context's 1D domain.
+constexpr int kTbMaxSteps = 16;
+int tb_cells_per_tile(int kb);
+hipError_t launch_step_tb(const StepParams& p, bool fp64, bool with_h, bool euler, int kb,
+                          bool seg, unsigned grid, hipStream_t s);
 // Batched segment step over `grid` workgroups (p.tiles has >= grid entries).
 hipError_t launch_seg_step(const StepParams& p, bool fp64, bool with_h, bool euler, unsigned grid,
                            hipStream_t s);

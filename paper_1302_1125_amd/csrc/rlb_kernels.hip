@@ -1086,6 +1086,326 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
 }
 
 // ---------------------------------------------------------------------------
+// Temporal blocking of 1D domains: one launch advances KB <= kTbMax steps.
+// A workgroup holds a region of kBlock consecutive cells (one per thread):
+// its populations and previous fields stay in registers across the steps and
+// the population values are exchanged through LDS once per step.  The star
+// stencil has radius 2, so after s steps the 2s cells at each end of a region
+// are stale; the workgroup owns the kBlock - 4 KB cells in the middle and
+// neighbouring regions overlap by 4 KB cells (computed twice, stored once).
+// HBM traffic per step falls by the factor KB.  Every owned cell takes the
+// single-step kernel's arithmetic in the same order; guard events and
+// inadmissible steps are counted by the owner only.  SEG: the region lies in
+// one segment of the serving arena (tile table entry (segment, tile)); a
+// segment whose steps are done keeps its state.
+// ---------------------------------------------------------------------------
+constexpr int kTbMax = kTbMaxSteps;
+
+#ifndef RLB_TB_OCC
+#define RLB_TB_OCC 2
+#endif
+template <typename T, bool WH, bool EU, bool SEG>
+__global__ __launch_bounds__(kBlock, RLB_TB_OCC) void k_step_tb(
+    const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ hin,
+    T* __restrict__ hout, double* __restrict__ hist, const uint8_t* __restrict__ obst,
+    const StepParams P, int KB) {
+  constexpr int R = kBlock;
+  constexpr int NA = WH ? 2 * Q : Q;
+  __shared__ T lds[NA][R + 2];  // slots R, R + 1: the fixed end states
+  const int p = static_cast<int>(threadIdx.x);
+  const int B = R - 4 * KB;
+  const long long S = P.pstride;
+  // the domain: n cells at storage indices base0 + [0, n), its end conditions
+  long long base0, face_lo, face_hi;
+  int n, bclo, bchi, tile, nupd;
+  long long step0;
+  double kappa_d = P.kappa, nu2e = P.nu2_etas, tau_u = P.tau;
+  unsigned long long* bad_ptr = P.bad_step;
+  unsigned long long* guard_ptr = P.guard_count;
+  if constexpr (SEG) {
+    const int2 t = P.tiles[blockIdx.x];
+    if (t.x < 0) return;  // the whole workgroup: no barrier is skipped
+    const SegDesc& sd = P.segs[t.x];
+    base0 = sd.base + 1;
+    face_lo = sd.base;
+    face_hi = sd.base + 1 + sd.n;
+    n = sd.n;
+    bclo = sd.bc_lo;
+    bchi = sd.bc_hi;
+    tile = t.y;
+    kappa_d = sd.kappa;
+    nu2e = sd.nu2_etas;
+    tau_u = sd.tau;
+    bad_ptr = sd.bad + sd.id;
+    guard_ptr = sd.guard + sd.id;
+    step0 = *P.gstep + P.step_in_chunk - sd.start;
+    const long long left = sd.steps - step0;
+    nupd = left <= 0 ? 0 : (left < KB ? static_cast<int>(left) : KB);
+  } else {
+    base0 = 0;
+    face_lo = P.ncell;
+    face_hi = P.ncell + 1;
+    n = P.nx;
+    bclo = P.bc[0];
+    bchi = P.bc[1];
+    tile = static_cast<int>(blockIdx.x);
+    step0 = P.step_index;
+    nupd = KB;
+  }
+  const bool periodic = bclo == kBcPeriodic;
+  const long long q = static_cast<long long>(tile) * B - 2 * KB + p;  // this lane's cell
+  const bool active = periodic || (q >= 0 && q < n);
+  const long long x = periodic ? ((q % n) + n) % n : (active ? q : 0);
+  const bool owned = p >= 2 * KB && p < 2 * KB + B && q >= 0 && q < n;
+  // LDS positions of the neighbours at offsets -2, -1, +1, +2 (periodic: the
+  // region holds the wrapped cells; fixed: the face slot; outflow: the end
+  // cell; positions past the region end are clamped and only feed stale lanes)
+  int pos[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = j < 2 ? j - 2 : j - 1;
+    const long long qq = q + k;
+    long long ps = p + k;
+    bool face = false;
+    if (!periodic && qq < 0) {
+      face = bclo == kBcFixed;
+      ps = face ? R : p - q;
+    } else if (!periodic && qq >= n) {
+      face = bchi == kBcFixed;
+      ps = face ? R + 1 : p - q + (n - 1);
+    }
+    if (!face) ps = ps < 0 ? 0 : (ps > R - 1 ? R - 1 : ps);
+    pos[j] = static_cast<int>(ps);
+  }
+  const long long cs = base0 + x;
+  const unsigned cl = static_cast<unsigned>(cs) * static_cast<unsigned>(sizeof(T));
+  const unsigned cd = static_cast<unsigned>(cs) * 8u;
+  const long long NC = P.ncell;
+  bool solid = false;
+  if constexpr (!SEG) solid = obst != nullptr && active && obst[cs] != 0;
+
+  // fixed end states (the face slots or the segment's ghost cells)
+  for (int a = p; a < 2 * NA; a += R) {
+    const int arr = a % NA, side = a / NA;
+    const long long at = side ? face_hi : face_lo;
+    const T* src = arr < Q ? fin + arr * S : hin + (arr - Q) * S;
+    lds[arr][R + side] = src[at];
+  }
+  T fc[Q];
+  T hc[Q];
+  double pe = 0.0, pux = 0.0, puy = 0.0, puz = 0.0, pn = 1.0;  // previous fields
+  if (active) {
+    static_for<0, Q>([&](auto I) {
+      fc[I] = ldb(fin + I * S, cl);
+      if constexpr (WH) hc[I] = ldb(hin + I * S, cl);
+    });
+    pe = ldb(hist, cd);
+    pux = ldb(hist + NC, cd);
+    puy = ldb(hist + 2 * NC, cd);
+    puz = ldb(hist + 3 * NC, cd);
+    pn = ldb(hist + 4 * NC, cd);
+  }
+  const T dtv = static_cast<T>(P.dtv);
+  constexpr T NA2 = T(2);
+
+  for (int st = 0; st < KB; ++st) {
+    __syncthreads();  // the previous step's neighbour reads are done
+    if (active) {
+      static_for<0, Q>([&](auto I) {
+        lds[I][p] = fc[I];
+        if constexpr (WH) lds[Q + I][p] = hc[I];
+      });
+    }
+    __syncthreads();
+    if (!active || solid || st >= nupd) continue;
+    const long long sidx = step0 + st;
+    // stencil of population I (axis x only) from the LDS row
+    auto sten = [&](auto I, int arr, bool lap, Sten<T>& sv) {
+      constexpr int ea = vcomp(I, 0);
+      if constexpr (ea > 0) {
+        sv.v[0][0] = lds[arr][pos[0]];
+        sv.v[0][1] = lds[arr][pos[1]];
+        sv.v[0][2] = lds[arr][pos[2]];
+      } else if constexpr (ea < 0) {
+        sv.v[0][0] = lds[arr][pos[1]];
+        sv.v[0][1] = lds[arr][pos[2]];
+        sv.v[0][2] = lds[arr][pos[3]];
+      } else {
+        if (lap) {
+          sv.v[0][0] = lds[arr][pos[1]];
+          sv.v[0][1] = lds[arr][pos[2]];
+        }
+      }
+    };
+    if constexpr (EU) {
+      const T kap = static_cast<T>(kappa_d);
+      double m0 = 0.0, mx = 0.0, my = 0.0, mz = 0.0, mh = 0.0;
+      static_for<0, Q>([&](auto I) {
+        constexpr Vel e = vel(I);
+        Sten<T> sf;
+        sten(I, I, I != 0, sf);
+        T dD, ns;
+        stream_terms<T, 1, I, (I != 0)>(sf, fc[I], dtv, dD, ns);
+        T v;
+        if constexpr (I != 0) v = (fc[I] - dD) + kap * (ns - NA2 * fc[I]);
+        else v = fc[I] - dD;
+        const double vd = static_cast<double>(v);
+        m0 += vd;
+        if constexpr (e.x != 0) mx += double(e.x) * vd;
+        if constexpr (e.y != 0) my += double(e.y) * vd;
+        if constexpr (e.z != 0) mz += double(e.z) * vd;
+        if constexpr (WH) {
+          Sten<T> sh;
+          sten(I, Q + I, false, sh);
+          T dH, nh;
+          stream_terms<T, 1, I, false>(sh, hc[I], dtv, dH, nh);
+          mh += static_cast<double>(hc[I] - dH);
+        }
+      });
+      const double E = P.r * P.r * m0, Mx = P.rca * mx, My = P.rca * my, Mz = P.rca * mz,
+                   N0 = P.r * mh;
+      Fields F;
+      bool ok = true, fired = false;
+      if (P.guard) {
+        double thf, thh;
+        fired = guard_eval<WH>(P, E, Mx, My, Mz, N0, thf, thh, F);
+        count_events(guard_ptr, fired && owned);
+      }
+      if (!fired) ok = recover<WH>(E, Mx, My, Mz, N0, F);
+      flag_bad(bad_ptr, !ok && owned, sidx);
+      double K[10];
+      feq_coeffs(P, F.eps, F.ux, F.uy, F.uz, F.g2, K);
+      T Kt[10];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) Kt[k] = static_cast<T>(K[k]);
+      static_for<0, Q>([&](auto I) { fc[I] = static_cast<T>(weight(I)) * bracket<I>(Kt); });
+      if constexpr (WH) {
+        double H[10];
+        heq_coeffs(P, F.n, F.ux, F.uy, F.uz, F.gam, H);
+        T Ht[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) Ht[k] = static_cast<T>(H[k]);
+        static_for<0, Q>([&](auto I) { hc[I] = static_cast<T>(wprime<I>(P)) * bracket<I>(Ht); });
+      }
+    } else {
+      double E, Mx, My, Mz, N0;
+      moments64<T, WH>(P, [&](auto I) { return fc[I]; }, [&](auto I) { return hc[I]; }, E, Mx, My,
+                       Mz, N0);
+      Fields F;
+      const bool ok = recover<WH>(E, Mx, My, Mz, N0, F);
+      flag_bad(bad_ptr, !ok && owned, sidx);
+      const double omega = P.omega_c / tau_of<T, WH>(P, F, tau_u, nu2e);
+      const double inv1p = 1.0 / (1.0 + omega);
+      const double src = omega * inv1p;
+      const double pg2 = 1.0 / (1.0 - (pux * pux + puy * puy + puz * puz));
+      T Kt[10];
+      {
+        double K[10], Kp[10];
+        feq_coeffs(P, F.eps, F.ux, F.uy, F.uz, F.g2, K);
+        feq_coeffs(P, pe, pux, puy, puz, pg2, Kp);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) Kt[k] = static_cast<T>(src * (2.0 * K[k] - Kp[k]));
+      }
+      T Ht[10];
+      if constexpr (WH) {
+        double H[10], Hp[10];
+        heq_coeffs(P, F.n, F.ux, F.uy, F.uz, F.gam, H);
+        heq_coeffs(P, pn, pux, puy, puz, sqrt(pg2), Hp);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) Ht[k] = static_cast<T>(src * (2.0 * H[k] - Hp[k]));
+      }
+      pe = F.eps;
+      pux = F.ux;
+      puy = F.uy;
+      puz = F.uz;
+      pn = F.n;
+      const T tinv = static_cast<T>(inv1p);
+      const T kinv = static_cast<T>(kappa_d * inv1p);
+      const T wp[3] = {static_cast<T>(P.wp0), static_cast<T>(P.wp1), static_cast<T>(P.wp2)};
+      T gE = T(0), gX = T(0), gY = T(0), gZ = T(0), gN = T(0), gA = T(0), gAh = T(0);
+      static_for<0, Q>([&](auto I) {
+        constexpr Vel e = vel(I);
+        Sten<T> sf;
+        sten(I, I, I != 0, sf);
+        T dD, ns;
+        stream_terms<T, 1, I, (I != 0)>(sf, fc[I], dtv, dD, ns);
+        T v = (fc[I] - dD) * tinv + static_cast<T>(weight(I)) * bracket<I>(Kt);
+        if constexpr (I != 0) v += kinv * (ns - NA2 * fc[I]);
+        fc[I] = v;
+        gE += v;
+        gA += fabs(v);
+        if constexpr (e.x != 0) gX += T(e.x) * v;
+        if constexpr (e.y != 0) gY += T(e.y) * v;
+        if constexpr (e.z != 0) gZ += T(e.z) * v;
+        if constexpr (WH) {
+          Sten<T> sh;
+          sten(I, Q + I, false, sh);
+          T dH, nh;
+          stream_terms<T, 1, I, false>(sh, hc[I], dtv, dH, nh);
+          const T wpi = I == 0 ? wp[0] : (I <= 6 ? wp[1] : wp[2]);
+          const T hv = (hc[I] - dH) * tinv + wpi * bracket<I>(Ht);
+          hc[I] = hv;
+          gN += hv;
+          gAh += fabs(hv);
+          asm volatile("" : "+v"(gN), "+v"(gAh));
+        }
+        asm volatile("" : "+v"(gE), "+v"(gA), "+v"(gX), "+v"(gY), "+v"(gZ));
+      });
+      if (P.guard) {
+        constexpr T tol = sizeof(T) == 4 ? T(8e-6) : T(1e-13);
+        const T r2 = static_cast<T>(P.r * P.r), rca = static_cast<T>(P.rca);
+        const T Eg = r2 * gE, mrg = tol * r2 * gA;
+        const T Mg = rca * sqrt(gX * gX + gY * gY + gZ * gZ);
+        bool need = !(Eg > mrg) || (Mg + mrg > static_cast<T>(P.m1) * (Eg - mrg));
+        if constexpr (WH) {
+          const T Ng = static_cast<T>(P.r) * gN;
+          need = need || !(Ng > static_cast<T>(2.0 * P.efloor * P.gmax) + tol * static_cast<T>(P.r) * gAh);
+        }
+        bool fired = false;
+        if (need) {
+          double E2, Mx2, My2, Mz2, N02;
+          moments64<T, WH>(P, [&](auto I) { return fc[I]; }, [&](auto I) { return hc[I]; }, E2,
+                           Mx2, My2, Mz2, N02);
+          double thf, thh;
+          Fields G;
+          fired = guard_eval<WH>(P, E2, Mx2, My2, Mz2, N02, thf, thh, G);
+          if (fired) {
+            double Kg[10];
+            feq_coeffs(P, G.eps, G.ux, G.uy, G.uz, G.g2, Kg);
+            static_for<0, Q>([&](auto I) {
+              const double ge = weight(I) * bracket<I>(Kg);
+              fc[I] = static_cast<T>(ge + thf * (static_cast<double>(fc[I]) - ge));
+            });
+            if constexpr (WH) {
+              double Hg[10];
+              heq_coeffs(P, G.n, G.ux, G.uy, G.uz, G.gam, Hg);
+              static_for<0, Q>([&](auto I) {
+                const double ge = wprime<I>(P) * bracket<I>(Hg);
+                hc[I] = static_cast<T>(ge + thh * (static_cast<double>(hc[I]) - ge));
+              });
+            }
+          }
+        }
+        count_events(guard_ptr, fired && owned);
+      }
+    }
+  }
+  if (owned) {
+    static_for<0, Q>([&](auto I) {
+      stb_nt(fout + I * S, cl, fc[I]);
+      if constexpr (WH) stb_nt(hout + I * S, cl, hc[I]);
+    });
+    if constexpr (!EU) {
+      stb_nt(hist, cd, pe);
+      stb_nt(hist + NC, cd, pux);
+      stb_nt(hist + 2 * NC, cd, puy);
+      stb_nt(hist + 3 * NC, cd, puz);
+      stb_nt(hist + 4 * NC, cd, pn);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Basic model (Sec. II): standard D3Q19 set, exact streaming (dt = c_t dx /
 // (c_a c_0) moves every population one link per step), explicit Marle
 // collision f' = f - omega (f - f^eq), omega = c_0 nu dt / (c_t tau); no
@@ -1396,6 +1716,32 @@ hipError_t launch_step(const StepParams& p, bool fp64, int act_mask, bool with_h
   }
   return fp64 ? launch_step_p<double>(p, act_mask, with_h, euler, s)
               : launch_step_p<float>(p, act_mask, with_h, euler, s);
+}
+
+namespace {
+template <typename T, bool WH, bool EU, bool SEG>
+void tb_t(const StepParams& p, int kb, unsigned grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_step_tb<T, WH, EU, SEG>), dim3(grid), dim3(kBlock), 0, s,
+                     static_cast<const T*>(p.f_in), static_cast<T*>(p.f_out),
+                     static_cast<const T*>(p.h_in), static_cast<T*>(p.h_out), p.hist,
+                     SEG ? nullptr : p.obst, p, kb);
+}
+template <typename T, bool SEG>
+void tb_p(const StepParams& p, bool with_h, bool euler, int kb, unsigned grid, hipStream_t s) {
+  if (with_h) euler ? tb_t<T, true, true, SEG>(p, kb, grid, s) : tb_t<T, true, false, SEG>(p, kb, grid, s);
+  else euler ? tb_t<T, false, true, SEG>(p, kb, grid, s) : tb_t<T, false, false, SEG>(p, kb, grid, s);
+}
+}  // namespace
+
+int tb_cells_per_tile(int kb) { return kBlock - 4 * kb; }
+
+hipError_t launch_step_tb(const StepParams& p, bool fp64, bool with_h, bool euler, int kb,
+                          bool seg, unsigned grid, hipStream_t s) {
+  if (kb < 1 || kb > kTbMax || p.lattice != 0) return hipErrorInvalidValue;
+  if (grid == 0) return hipSuccess;
+  if (fp64) seg ? tb_p<double, true>(p, with_h, euler, kb, grid, s) : tb_p<double, false>(p, with_h, euler, kb, grid, s);
+  else seg ? tb_p<float, true>(p, with_h, euler, kb, grid, s) : tb_p<float, false>(p, with_h, euler, kb, grid, s);
+  return hipGetLastError();
 }
 
 namespace {

@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -67,6 +68,8 @@ struct rlb_server {
   size_t elem = 4;
   long long cap = 0, pstride = 0;
   int max_slots = 0, chunk = 64;
+  int tb = 1;          // steps per temporally blocked launch (1: one step per launch)
+  int tile_cells = rlb::kBlock;  // cells per workgroup tile
   int device = 0;
   hipStream_t stream = nullptr;
   void* f[2] = {nullptr, nullptr};
@@ -199,14 +202,16 @@ hipError_t graph_for(rlb_server* s, unsigned grid, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
-  for (int j = 0; j < s->chunk && e == hipSuccess; ++j) {
+  // chunk / tb launches (an even number, so the chunk ends on copy 0)
+  for (int j = 0; j < s->chunk / s->tb && e == hipSuccess; ++j) {
     rlb::StepParams p = s->base;
     p.f_in = s->f[j % 2];
     p.f_out = s->f[(j + 1) % 2];
     p.h_in = s->h[j % 2];
     p.h_out = s->h[(j + 1) % 2];
-    p.step_in_chunk = j;
-    e = rlb::launch_seg_step(p, s->fp64, s->with_h, s->euler, grid, s->stream);
+    p.step_in_chunk = j * s->tb;
+    e = s->tb > 1 ? rlb::launch_step_tb(p, s->fp64, s->with_h, s->euler, s->tb, true, grid, s->stream)
+                  : rlb::launch_seg_step(p, s->fp64, s->with_h, s->euler, grid, s->stream);
   }
   hipError_t e2 = hipStreamEndCapture(s->stream, &g);
   if (e == hipSuccess) e = e2;
@@ -298,7 +303,7 @@ hipError_t upload_tables(rlb_server* s) {
   long long nt = 0;
   for (uint64_t id : s->active) {
     const Req& r = s->reqs[id];
-    const int tiles = (r.n + rlb::kBlock - 1) / rlb::kBlock;
+    const int tiles = (r.n + s->tile_cells - 1) / s->tile_cells;
     for (int t = 0; t < tiles; ++t) s->h_tiles[nt++] = make_int2(r.slot, t);
   }
   s->grid = static_cast<unsigned>(round_up(std::max<long long>(nt, 1), kGridBucket));
@@ -524,8 +529,23 @@ rlb_status rlb_server_create(const rlb_config* common, uint64_t budget_bytes, in
   s->cap = cap;
   s->pstride = rlb::population_stride(cap);
   s->chunk = chunk_steps;
+  {
+    // temporal blocking: the largest tb <= the requested steps per launch
+    // (default 8; RLB_TB_STEPS tuning override, 1 = off) with an even number
+    // of launches per chunk
+    int want = 8;
+    if (const char* v = std::getenv("RLB_TB_STEPS")) want = std::atoi(v);
+    want = std::max(1, std::min(want, rlb::kTbMaxSteps));
+    s->tb = 1;
+    for (int d = want; d > 1; --d)
+      if (chunk_steps % (2 * d) == 0) {
+        s->tb = d;
+        break;
+      }
+    s->tile_cells = s->tb > 1 ? rlb::tb_cells_per_tile(s->tb) : rlb::kBlock;
+  }
   s->max_slots = static_cast<int>(std::min<long long>(65536, cap / kAlign));
-  s->max_tiles = round_up(cap / rlb::kBlock + s->max_slots + 1, kGridBucket);
+  s->max_tiles = round_up(cap / s->tile_cells + s->max_slots + 1, kGridBucket);
   hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
   const size_t pop = static_cast<size_t>(rlb::Q) * s->pstride * s->elem;
   for (int k = 0; k < 2 && e == hipSuccess; ++k) {
