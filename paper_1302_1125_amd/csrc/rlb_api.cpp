@@ -568,6 +568,11 @@ rlb_status rlb_moments(rlb_ctx* x, double* eps, double* ux, double* uy, double* 
   return RLB_OK;
 }
 
+int32_t rlb_steps_per_launch(const rlb_ctx* x) {
+  if (!x) return 0;
+  return (x->act_mask == 1 && x->cfg.lattice == RLB_LATTICE_EXTENDED) ? x->tb_steps : 1;
+}
+
 rlb_status rlb_stats_get(rlb_ctx* x, rlb_stats* out) {
   if (!x || !out) return fail(RLB_E_INVALID_ARG, "NULL argument");
   if (!x->initialised) return fail(RLB_E_STATE, "rlb_init_fields has not been called");

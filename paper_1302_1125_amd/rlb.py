@@ -32,7 +32,7 @@ RLB_LATTICE_EXTENDED, RLB_LATTICE_BASIC = 0, 1
 EXPORTED = [
     "rlb_config_default", "rlb_create", "rlb_init_fields", "rlb_step", "rlb_step_async",
     "rlb_sync", "rlb_moments", "rlb_stats_get", "rlb_destroy", "rlb_status_str",
-    "rlb_last_error", "rlb_footprint_bytes",
+    "rlb_last_error", "rlb_footprint_bytes", "rlb_steps_per_launch",
 ]
 
 
@@ -100,6 +100,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.rlb_last_error.restype = ctypes.c_char_p
     L.rlb_footprint_bytes.argtypes = [ctypes.POINTER(rlb_config)]
     L.rlb_footprint_bytes.restype = ctypes.c_uint64
+    L.rlb_steps_per_launch.argtypes = [vp]
+    L.rlb_steps_per_launch.restype = ctypes.c_int32
     for name in ("rlb_config_default", "rlb_create", "rlb_init_fields", "rlb_step",
                  "rlb_step_async", "rlb_sync", "rlb_moments", "rlb_stats_get"):
         getattr(L, name).restype = ctypes.c_int
@@ -214,6 +216,9 @@ class Context:
 
     def rlb_sync(self):
         _check(self._L.rlb_sync(self._h))
+
+    def rlb_steps_per_launch(self) -> int:
+        return int(self._L.rlb_steps_per_launch(self._h))
 
     def rlb_moments(self):
         """(eps, ux, uy, uz, n) as float64 arrays of shape [nz, ny, nx]."""

@@ -129,3 +129,10 @@ def test_basic_lattice_validation():
         cfg = rlb.config_from(32, 8, 4, bc=per, lattice=rlb.RLB_LATTICE_BASIC, **bad)
         assert rlb.rlb_footprint_bytes(cfg) == 0, bad
     assert rlb.rlb_footprint_bytes(rlb.config_from(32, 8, 4, bc=per, lattice=2)) == 0
+
+
+def test_steps_per_launch_of_null_context():
+    from paper_1302_1125_amd import rlb
+    if not os.path.exists(rlb.LIB_PATH):
+        pytest.skip("librlb.so not built")
+    assert rlb.load().rlb_steps_per_launch(None) == 0

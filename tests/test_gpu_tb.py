@@ -129,3 +129,17 @@ def test_tb_mixed_tube_against_oracle(rlb):
     assert o.step(500) == 0
     errs = field_errors(a, o.fields())
     assert errs["eps"] <= 2e-5 and errs["n"] <= 2e-5 and errs["gux"] <= 2e-4, errs
+
+
+def test_steps_per_launch(rlb):
+    w1 = W.shock_tube_1d()
+    ctx = rlb.context_for_workload(w1)
+    assert ctx.rlb_steps_per_launch() == 8
+    ctx.close()
+    w3 = W.random_smooth_state(8, 8, 8, seed=1)
+    ctx = rlb.context_for_workload(w3)
+    assert ctx.rlb_steps_per_launch() == 1
+    ctx.close()
+    ctx = rlb.context_for_workload(W.as_basic(W.shock_tube_1d()))
+    assert ctx.rlb_steps_per_launch() == 1
+    ctx.close()
