@@ -1101,11 +1101,21 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
 // ---------------------------------------------------------------------------
 constexpr int kTbMax = kTbMaxSteps;
 
-#ifndef RLB_TB_OCC
-#define RLB_TB_OCC 2
+// waves per SIMD the register allocator must allow (measured: FP32 3, which
+// spills a few registers in the guarded implicit path but runs large domains
+// 8-10% faster than 2; FP64 2)
+#ifndef RLB_TB_OCC_F32
+#define RLB_TB_OCC_F32 3
 #endif
+#ifndef RLB_TB_OCC_F64
+#define RLB_TB_OCC_F64 2
+#endif
+template <typename T>
+struct TbOcc {
+  static constexpr int value = sizeof(T) == 4 ? RLB_TB_OCC_F32 : RLB_TB_OCC_F64;
+};
 template <typename T, bool WH, bool EU, bool SEG>
-__global__ __launch_bounds__(kBlock, RLB_TB_OCC) void k_step_tb(
+__global__ __launch_bounds__(kBlock, (TbOcc<T>::value)) void k_step_tb(
     const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ hin,
     T* __restrict__ hout, double* __restrict__ hist, const uint8_t* __restrict__ obst,
     const StepParams P, int KB) {
