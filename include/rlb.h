@@ -249,7 +249,11 @@ typedef struct {
    arena (populations, ping-pong, previous fields; at most 2^28 - 128 cells
    are used); chunk_steps: steps per
    graph launch, even, >= 2.  The server runs on a stream it creates.
-   The extended lattice only (RLB_E_INVALID_ARG for RLB_LATTICE_BASIC). */
+   The extended lattice only (RLB_E_INVALID_ARG for RLB_LATTICE_BASIC).
+   Each launch of a chunk advances every resident request by up to 8 steps
+   with the state held on chip (temporal blocking; the largest depth <= 8,
+   or <= RLB_TB_STEPS from the environment, that gives an even number of
+   launches per chunk; results equal one step per launch to rounding). */
 rlb_status rlb_server_create(const rlb_config* common, uint64_t budget_bytes, int32_t chunk_steps,
                              rlb_server** out);
 
