@@ -220,6 +220,23 @@ def test_mixed_precision_errors(rlb, which):
         assert v <= MIXED_BOUNDS[k], (k, v, errs)
 
 
+def test_colliding_slabs_mixed_errors(rlb):
+    """The gamma = 10 colliding slabs (guard on) in mixed precision against the
+    FP64 oracle, per field, at 10 steps.  The guarded slabs amplify rounding
+    differences about 3x per step (a one-ulp FP64 perturbation reaches 1e-4
+    in n by step 50), so the mixed-precision bound is stated at 10 steps:
+    eps <= 5e-5, n and gamma u <= 2e-4 (measured 1.7e-5, 5.0e-5, 7.0e-5)."""
+    w, steps = W.colliding_slabs_1d(steps=10), 10
+    _case("mixed slabs", w, steps)
+    g, _ = _run_gpu(rlb, w, steps, precision=W.MIXED)
+    o, _ = _run_oracle(w, steps)
+    errs = field_errors(g, o, keys=("eps", "p", "n", "gux"))
+    print("mixed-precision rel. L2 errors (slabs, 10 steps):", errs)
+    bounds = {"eps": 5e-5, "p": 5e-5, "n": 2e-4, "gux": 2e-4}
+    for k, v in errs.items():
+        assert v <= bounds[k], (k, v, errs)
+
+
 def test_inadmissible_step_index_matches_oracle(rlb):
     w = W.colliding_slabs_1d(nx=512, steps=100, guard_umax=0.0)
     _case("inadmissible", w, 100)
