@@ -34,8 +34,11 @@
  *     extended set); ghost edges needed by the diagonal links are filled axis
  *     by axis (x, then y over the x ghosts, then z), so a later axis's FIXED
  *     face wins at an edge.
- * Parity unpinned: the viscosity calibration of Eq. (41) in the extended
- * scheme (the paper's comparison data are not available).
+ * The shear viscosity the scheme realises is pinned by a Chapman-Enskog
+ * expansion (tests/test_oracle_viscosity.py): eta/(eps+p) = (4/27) times the
+ * relaxation time (basic: (1/omega - 1/2) dt; extended: dt/omega), which
+ * differs from Eq. (41) by the factor 4/sqrt(27) on tau; the eta/s mode
+ * uses Eq. (41) as printed.
  */
 #include "rlb_oracle.h"
 
