@@ -146,3 +146,36 @@ def test_requests_arriving_while_others_run(rlb):
     assert ref[2] == outs[3][2]  # same first inadmissible step (or none)
     for a, b in zip(ref[0], outs[3][0]):
         assert np.array_equal(a, b, equal_nan=True)
+
+
+@pytest.mark.parametrize("ends", [(W.BC_OUTFLOW, W.BC_OUTFLOW), (W.BC_PERIODIC, W.BC_PERIODIC),
+                                  (W.BC_FIXED, W.BC_OUTFLOW)])
+def test_segment_ends_equal_context_path_and_oracle(rlb, ends):
+    """Requests with outflow, periodic or mixed ends (the temporally blocked
+    segment kernel maps each end like the context kernel): served results
+    equal the context path bit for bit, and the FP64 oracle wherever the
+    guard stays idle (a request in which it fires is chaotic: the oracle's
+    own one-ulp perturbation grows to 1e-4 there)."""
+    import dataclasses
+    reqs = [dataclasses.replace(q, bc_lo=ends[0], bc_hi=ends[1])
+            for q in _mix(k=4, seed=29, nmin=300, nmax=900, steps_factor=0.25)]
+    common = _common(rlb, precision=W.FP64)
+    outs, st = _serve(rlb, common, reqs)
+    assert st.completed == len(reqs) and st.failed == 0
+    compared = 0
+    for q, out in zip(reqs, outs):
+        w = q.workload(precision=W.FP64, nu=NU)
+        ctx = rlb.context_for_workload(w, precision=W.FP64)
+        ctx.rlb_step(q.steps)
+        ref = ctx.rlb_moments()
+        ctx.close()
+        for a, b in zip(out[0], ref):
+            assert np.array_equal(a, b.ravel())
+        o = oracle_for(w)
+        assert o.step(q.steps) == 0
+        if o.guard_events:
+            continue
+        compared += 1
+        errs = field_errors([a.reshape(w.shape) for a in out[0]], o.fields(), keys=("eps", "p", "n", "gux"))
+        assert max(errs.values()) <= 1e-10, errs
+    assert compared >= 2
