@@ -1,0 +1,215 @@
+"""Linear stability of uniform flows: the oracle's time step against a von
+Neumann analysis built from the lattice tables and the equilibria (CPU only).
+
+A uniform state at rest or in motion is a fixed point of the scheme (pinned
+in test_oracle_step).  Perturb it along x by a small multiple of (-1)^x, the
+shortest wave (theta = pi).  Every population then has one-sided
+differences of opposite sign at every cell, so the minmod correction of the
+limited flux (Sec. II.B, Eqs. (46)-(49)) is exactly zero and the step acts on
+the perturbation as first-order upwind streaming.  Linearised about the
+uniform state, one step is a fixed matrix per Fourier mode theta:
+  - streaming of population i with speed p_i = (c_0/c_t) xi_i^x:
+      S_i = 1 - |p_i| dt (1 - exp(-i theta sgn p_i));
+  - bulk term (f only, i != 0, Eq. (55)): + kappa (2 cos theta - 2),
+      kappa = (c_0 nu/c_t) alpha dt;
+  - implicit update (Eq. (57)), omega = (c_0 nu/c_t) dt / tau:
+      f' = [S f + omega (2 J K f - J U_prev)] / (1 + omega),  U_prev' = K f,
+    with K the moment map f -> (T^00, T^0a) and J = d f^eq / d(T^00, T^0a)
+    at the uniform state (recovery, then the equilibrium);
+  - Euler mode (Sec. III): f' = J K S f;
+  - density part at fixed u: h^eq = n h^eq(n = 1, u), n = N^0 / gamma with
+    N^0 = k . h, and the same update with history n_prev.
+K, J and k come from the oracle's moment, recovery and equilibrium
+functions, which are pinned by the tables tests; the streaming, bulk term,
+implicit update, history and Euler reset of the oracle's step are not used.
+The test propagates the initial perturbation with these matrices and
+compares every population of the oracle after each step.
+
+Maximised over theta, the same matrices give the stability envelope of the
+scheme as read for uniform flows along a lattice axis (asserted below):
+  - energy-momentum part (tau = 1, dt = 0.25): stable for |u| <= 0.4; the
+    growth per step is 0.0002 at u = 0.5, 0.0047 at 0.7 and 0.029 at 0.8,
+    largest for the shortest wave.  Per unit time it does not depend on dt,
+    so it is a property of the upwind discretisation in space with this
+    equilibrium, not a time-step condition; it falls with tau but stays
+    positive for every tau;
+  - density part (tau = 1, dt = 0.25): with nu = 27^(1/4) uniform flows are
+    unstable from |u| ~ 0.2 (0.024 per step at u = 0.4, for waves about 8
+    cells long; the shortest wave is damped except in the Euler mode); for
+    nu between about 3.2 and 7 the density part is stable for every
+    |u| <= 0.99; nu = 9 is unstable again from |u| ~ 0.8.
+"""
+import math
+
+import numpy as np
+import pytest
+
+NU0 = 27.0 ** 0.25
+NX = 16
+
+
+def _fd(fun, x0, k, h):
+    xp, xm = np.array(x0, dtype=float), np.array(x0, dtype=float)
+    xp[k] += h
+    xm[k] -= h
+    return (fun(xp) - fun(xm)) / (2.0 * h)
+
+
+def _speeds(O, nu):
+    e, xi, w, wp = O.lattice(nu)
+    assert (e[0] == 0).all()  # population 0 is the rest particle
+    return xi[:, 1] * nu / math.sqrt(27.0)  # p_i = (c_0 / c_t) xi_i^x
+
+
+def _stream(p, dt, theta, kappa=0.0):
+    s = 1.0 - np.abs(p) * dt * (1.0 - np.exp(-1j * theta * np.sign(p)))
+    lap = kappa * (2.0 * math.cos(theta) - 2.0) * (np.arange(p.size) != 0)
+    return s + lap
+
+
+def _f_linear(O, nu, u):
+    """K (4 x 19), J (19 x 4), d f^eq / d eps and d eps / d U at eps = 3."""
+    q = 19
+    K = np.stack([O.moments(nu, np.eye(q)[i])[0] for i in range(q)], 1)
+    U0 = O.moments(nu, O.feq(nu, 3.0, u, 0.0, 0.0))[0]
+
+    def feq_of_U(U):
+        rc, fl = O.recover(U, 0.0, with_h=False)
+        assert rc == 0
+        return O.feq(nu, fl[0], fl[1], fl[2], fl[3])
+
+    def eps_of_U(U):
+        return np.array([O.recover(U, 0.0, with_h=False)[1][0]])
+
+    hU = 1e-5 * U0[0]
+    J = np.stack([_fd(feq_of_U, U0, k, hU) for k in range(4)], 1)
+    dfe = _fd(lambda v: O.feq(nu, v[0], u, 0.0, 0.0), [3.0], 0, 1e-5)
+    deps = np.array([_fd(eps_of_U, U0, k, hU)[0] for k in range(4)])
+    return K, J, dfe, deps
+
+
+def _f_matrix(O, nu, u, dt, tau, alpha, theta, lin=None):
+    K, J, _, _ = lin or _f_linear(O, nu, u)
+    kappa = nu * nu / math.sqrt(27.0) * alpha * dt
+    S = np.diag(_stream(_speeds(O, nu), dt, theta, kappa))
+    if tau is None:  # Euler mode
+        return J @ K @ S
+    om = nu * nu * dt / (math.sqrt(27.0) * tau)
+    G = np.zeros((23, 23), complex)
+    G[:19, :19] = (S + 2.0 * om * J @ K) / (1.0 + om)
+    G[:19, 19:] = -om * J / (1.0 + om)
+    G[19:, :19] = K
+    return G
+
+
+def _h_linear(O, nu, u):
+    q = 19
+    f0 = O.feq(nu, 3.0, u, 0.0, 0.0)
+    k = np.array([O.moments(nu, f0, np.eye(q)[i])[1] for i in range(q)])
+    gamma = 1.0 / math.sqrt(1.0 - u * u)
+    return O.heq(nu, 1.0, u, 0.0, 0.0), k / gamma
+
+
+def _h_matrix(O, nu, u, dt, tau, theta):
+    he1, kn = _h_linear(O, nu, u)
+    S = np.diag(_stream(_speeds(O, nu), dt, theta))
+    if tau is None:
+        return np.outer(he1, kn) @ S
+    om = nu * nu * dt / (math.sqrt(27.0) * tau)
+    G = np.zeros((20, 20), complex)
+    G[:19, :19] = (S + 2.0 * om * np.outer(he1, kn)) / (1.0 + om)
+    G[:19, 19] = -om * he1 / (1.0 + om)
+    G[19, :19] = kn
+    return G
+
+
+def _growth(G_of_theta, nth=181):
+    """Largest log spectral radius over theta in [0, pi] (per step)."""
+    return max(math.log(max(abs(np.linalg.eigvals(G_of_theta(t))))) for t in np.linspace(0, math.pi, nth))
+
+
+def _odd_even(O, cfg, init, x0, G, steps, part):
+    sgn = (-1.0) ** np.arange(NX)
+    o = O.Oracle(cfg)
+    o.init(*init)
+    x = x0
+    worst = 0.0
+    for _ in range(steps):
+        assert o.step(1) == 0
+        x = G @ x
+        f, h = o.pops()
+        pops = f if part == "f" else h
+        meas = (pops * sgn).mean(axis=1)
+        pred = x[:19]
+        worst = max(worst, float(np.abs(meas - pred).max() / np.abs(pred).max()))
+    return worst, float(np.abs(x[:19]).max() / np.abs(x0[:19]).max())
+
+
+@pytest.mark.parametrize("nu,u,dt,tau,alpha,steps,grows", [
+    (NU0, 0.8, 0.25, 1.0, 0.0, 100, True),    # grows e^{0.029} per step
+    (NU0, 0.3, 0.25, 0.8, 0.2, 10, False),    # damped, with the bulk term
+    (NU0, 0.75, 0.25, None, 0.0, 60, True),   # Euler mode
+    (4.0, 0.5, 0.15, 0.6, 0.2, 10, False),    # another nu (omega, kappa)
+])
+def test_energy_part_shortest_wave_follows_linear_theory(oracle_mod, nu, u, dt, tau, alpha, steps, grows):
+    O = oracle_mod
+    amp = 1e-6
+    lin = _f_linear(O, nu, u)
+    K, J, dfe, deps = lin
+    G = _f_matrix(O, nu, u, dt, tau, alpha, math.pi, lin).real
+    x0 = dfe * amp if tau is None else np.concatenate([dfe * amp, K @ dfe * amp])
+    cfg = O.Config(nx=NX, nu=nu, dt=dt, tau_mode=O.TAU_UNIFORM, tau=tau or 1.0, alpha=alpha,
+                   euler=tau is None, bc=[O.BC_PERIODIC] * 6)
+    z = np.zeros(NX)
+    init = (3.0 + amp * (-1.0) ** np.arange(NX), np.full(NX, u), z, z, None)
+    worst, gain = _odd_even(O, cfg, init, x0, G, steps, "f")
+    print(f"max rel. deviation from the linear prediction {worst:.1e}, gain {gain:.3g}")
+    assert worst < 1e-5, worst
+    assert (gain > 2.0) if grows else (gain < 1.0)
+
+
+@pytest.mark.parametrize("nu,u,tau,steps,grows", [
+    (NU0, 0.6, None, 40, True),   # Euler mode: the shortest wave grows e^{0.18} per step
+    (NU0, 0.5, 1.0, 10, False),   # implicit: the shortest wave is damped (longer ones grow)
+    (4.0, 0.8, 1.0, 10, False),   # all density weights positive
+])
+def test_density_part_shortest_wave_follows_linear_theory(oracle_mod, nu, u, tau, steps, grows):
+    O = oracle_mod
+    amp, dt = 1e-6, 0.25
+    he1, kn = _h_linear(O, nu, u)
+    G = _h_matrix(O, nu, u, dt, tau, math.pi).real
+    x0 = he1 * amp if tau is None else np.concatenate([he1 * amp, [amp]])
+    cfg = O.Config(nx=NX, nu=nu, dt=dt, tau_mode=O.TAU_UNIFORM, tau=tau or 1.0,
+                   euler=tau is None, with_h=True, bc=[O.BC_PERIODIC] * 6)
+    z = np.zeros(NX)
+    init = (np.full(NX, 3.0), np.full(NX, u), z, z, 1.0 + amp * (-1.0) ** np.arange(NX))
+    worst, gain = _odd_even(O, cfg, init, x0, G, steps, "h")
+    print(f"max rel. deviation from the linear prediction {worst:.1e}, gain {gain:.3g}")
+    assert worst < 1e-5, worst
+    assert (gain > 2.0) if grows else (gain < 1.0)
+
+
+def test_stability_envelope_of_uniform_flows(oracle_mod):
+    O = oracle_mod
+
+    def gf(u, dt=0.25, tau=1.0):
+        lin = _f_linear(O, NU0, u)
+        return _growth(lambda t: _f_matrix(O, NU0, u, dt, tau, 0.0, t, lin))
+
+    for u in (0.0, 0.2, 0.4):
+        assert gf(u) < 1e-9
+    g8 = gf(0.8)
+    assert 0.025 < g8 < 0.033
+    # per unit time the growth does not depend on dt (a spatial property)
+    assert abs(gf(0.8, dt=0.1) / 0.1 / (g8 / 0.25) - 1.0) < 0.05
+    # it falls with tau but stays positive
+    assert 0.0 < gf(0.8, tau=20.0) < gf(0.8, tau=2.0) < g8
+
+    def gh(nu, u):
+        return _growth(lambda t: _h_matrix(O, nu, u, 0.25, 1.0, t))
+
+    assert gh(NU0, 0.4) > 0.02
+    for nu in (3.5, 5.0):
+        for u in (0.2, 0.6, 0.9, 0.99):
+            assert gh(nu, u) < 1e-9
+    assert gh(9.0, 0.9) > 0.005
