@@ -56,22 +56,35 @@ def _fd(fun, x0, k, h):
 
 
 def _speeds(O, nu):
+    """(19, 3) streaming velocities p_i^a = (c_0 / c_t) xi_i^a."""
     e, xi, w, wp = O.lattice(nu)
     assert (e[0] == 0).all()  # population 0 is the rest particle
-    return xi[:, 1] * nu / math.sqrt(27.0)  # p_i = (c_0 / c_t) xi_i^x
+    return xi[:, 1:] * nu / math.sqrt(27.0)
 
 
 def _stream(p, dt, theta, kappa=0.0):
-    s = 1.0 - np.abs(p) * dt * (1.0 - np.exp(-1j * theta * np.sign(p)))
-    lap = kappa * (2.0 * math.cos(theta) - 2.0) * (np.arange(p.size) != 0)
+    """Per-population factor of one upwind step and bulk term for the Fourier
+    mode exp(i theta . x); theta is a number (x only) or a 3-vector."""
+    th = np.zeros(3)
+    th[:np.size(theta)] = theta
+    s = 1.0 - (np.abs(p) * dt * (1.0 - np.exp(-1j * th * np.sign(p)))).sum(axis=1)
+    lap = kappa * (2.0 * np.cos(th) - 2.0).sum() * (np.arange(p.shape[0]) != 0)
     return s + lap
 
 
+def _vel(u):
+    v = np.zeros(3)
+    v[:np.size(u)] = u
+    return v
+
+
 def _f_linear(O, nu, u):
-    """K (4 x 19), J (19 x 4), d f^eq / d eps and d eps / d U at eps = 3."""
+    """K (4 x 19), J (19 x 4), d f^eq / d eps and d eps / d U at eps = 3 and
+    velocity u (a number: along x; or a 3-vector)."""
     q = 19
+    ux, uy, uz = _vel(u)
     K = np.stack([O.moments(nu, np.eye(q)[i])[0] for i in range(q)], 1)
-    U0 = O.moments(nu, O.feq(nu, 3.0, u, 0.0, 0.0))[0]
+    U0 = O.moments(nu, O.feq(nu, 3.0, ux, uy, uz))[0]
 
     def feq_of_U(U):
         rc, fl = O.recover(U, 0.0, with_h=False)
@@ -83,7 +96,7 @@ def _f_linear(O, nu, u):
 
     hU = 1e-5 * U0[0]
     J = np.stack([_fd(feq_of_U, U0, k, hU) for k in range(4)], 1)
-    dfe = _fd(lambda v: O.feq(nu, v[0], u, 0.0, 0.0), [3.0], 0, 1e-5)
+    dfe = _fd(lambda v: O.feq(nu, v[0], ux, uy, uz), [3.0], 0, 1e-5)
     deps = np.array([_fd(eps_of_U, U0, k, hU)[0] for k in range(4)])
     return K, J, dfe, deps
 
@@ -104,10 +117,11 @@ def _f_matrix(O, nu, u, dt, tau, alpha, theta, lin=None):
 
 def _h_linear(O, nu, u):
     q = 19
-    f0 = O.feq(nu, 3.0, u, 0.0, 0.0)
+    ux, uy, uz = _vel(u)
+    f0 = O.feq(nu, 3.0, ux, uy, uz)
     k = np.array([O.moments(nu, f0, np.eye(q)[i])[1] for i in range(q)])
-    gamma = 1.0 / math.sqrt(1.0 - u * u)
-    return O.heq(nu, 1.0, u, 0.0, 0.0), k / gamma
+    gamma = 1.0 / math.sqrt(1.0 - ux * ux - uy * uy - uz * uz)
+    return O.heq(nu, 1.0, ux, uy, uz), k / gamma
 
 
 def _h_matrix(O, nu, u, dt, tau, theta):
@@ -128,10 +142,20 @@ def _growth(G_of_theta, nth=181):
     return max(math.log(max(abs(np.linalg.eigvals(G_of_theta(t))))) for t in np.linspace(0, math.pi, nth))
 
 
-def _odd_even(O, cfg, init, x0, G, steps, part):
-    sgn = (-1.0) ** np.arange(NX)
+def _checkerboard(shape, axes=(0, 1, 2)):
+    """(-1)^(sum of the coordinates along `axes`), flattened in [z][y][x] order."""
+    z, y, x = np.indices(shape)
+    c = (x, y, z)
+    return ((-1.0) ** sum(c[a] for a in axes)).reshape(-1)
+
+
+def _odd_even(O, cfg, init, x0, G, steps, part, axes=(0, 1, 2)):
+    """Largest deviation (relative to the largest predicted population) of the
+    oracle's checkerboard amplitudes from the linear prediction, and the
+    predicted gain after `steps` steps."""
     o = O.Oracle(cfg)
     o.init(*init)
+    sgn = _checkerboard(o.shape, axes)
     x = x0
     worst = 0.0
     for _ in range(steps):
@@ -213,3 +237,45 @@ def test_stability_envelope_of_uniform_flows(oracle_mod):
         for u in (0.2, 0.6, 0.9, 0.99):
             assert gh(nu, u) < 1e-9
     assert gh(9.0, 0.9) > 0.005
+
+
+@pytest.mark.parametrize("u,axes,dt,tau,alpha,steps", [
+    ((0.5, 0.3, 0.2), (0, 1, 2), 0.15, 0.7, 0.2, 5),   # theta = (pi, pi, pi), bulk term on
+    ((0.6, 0.4, 0.2), (0, 1), 0.25, 1.0, 0.0, 30),     # theta = (pi, pi, 0)
+])
+def test_checkerboard_3d_energy_part(oracle_mod, u, axes, dt, tau, alpha, steps):
+    """(-1)^(x+y+z) or (-1)^(x+y) on a periodic 4x4x4 grid with an oblique
+    flow: minmod is idle along every axis, so streaming along all three axes,
+    the 3D Laplacian and the update are checked at theta = (pi, pi, pi) and
+    (pi, pi, 0).  These short waves are damped in oblique flows."""
+    O = oracle_mod
+    amp, shape = 1e-5, (4, 4, 4)
+    lin = _f_linear(O, NU0, u)
+    K, J, dfe, deps = lin
+    th = np.array([math.pi if a in axes else 0.0 for a in range(3)])
+    G = _f_matrix(O, NU0, u, dt, tau, alpha, th, lin).real
+    x0 = np.concatenate([dfe * amp, K @ dfe * amp])
+    cfg = O.Config(nx=4, ny=4, nz=4, nu=NU0, dt=dt, tau_mode=O.TAU_UNIFORM, tau=tau, alpha=alpha,
+                   bc=[O.BC_PERIODIC] * 6)
+    ones = np.ones(shape)
+    init = (3.0 + amp * _checkerboard(shape, axes).reshape(shape), u[0] * ones, u[1] * ones, u[2] * ones, None)
+    worst, gain = _odd_even(O, cfg, init, x0, G, steps, "f", axes)
+    print(f"max rel. deviation from the linear prediction {worst:.1e}, gain {gain:.3g}")
+    assert worst < 1e-5, worst
+    assert 0.01 < gain < 1.0
+
+
+def test_checkerboard_3d_density_part(oracle_mod):
+    O = oracle_mod
+    amp, shape, u, dt = 1e-6, (4, 4, 4), (0.3, 0.3, 0.1), 0.15
+    he1, kn = _h_linear(O, NU0, u)
+    G = _h_matrix(O, NU0, u, dt, 0.8, np.full(3, math.pi)).real
+    x0 = np.concatenate([he1 * amp, [amp]])
+    cfg = O.Config(nx=4, ny=4, nz=4, nu=NU0, dt=dt, tau_mode=O.TAU_UNIFORM, tau=0.8, with_h=True,
+                   bc=[O.BC_PERIODIC] * 6)
+    ones = np.ones(shape)
+    init = (3.0 * ones, u[0] * ones, u[1] * ones, u[2] * ones,
+            1.0 + amp * _checkerboard(shape).reshape(shape))
+    worst, gain = _odd_even(O, cfg, init, x0, G, 10, "h")
+    print(f"max rel. deviation from the linear prediction {worst:.1e}, gain {gain:.3g}")
+    assert worst < 1e-5, worst
