@@ -195,20 +195,32 @@ def serving(args):
     def log(msg):
         print(f"[serving] {msg}", file=sys.stderr, flush=True)
 
-    nu = args.serving_nu
+    nu, dt = args.serving_nu, 0.25
+    if args.serving_stabilised:
+        nu, dt = W.STABILISED["nu"], W.STABILISED["dt"]
     common = rlb.config_from(8, precision=rlb.RLB_MIXED, tau_mode=rlb.RLB_TAU_ETA_OVER_S,
-                             with_density=True, dt_over_dx=0.25, guard_umax=0.9999, nu=nu)
+                             with_density=True, dt_over_dx=dt, guard_umax=0.9999, nu=nu)
+
+    def prepare(qs):
+        # the stabilised parameter set: bulk term alpha, and the same physical
+        # run time (2n steps of dt = 0.25) in steps of the smaller dt
+        if args.serving_stabilised:
+            for q in qs:
+                q.alpha = W.STABILISED["alpha"]
+                q.steps = int(round(q.steps * 0.25 / dt))
+        return qs
+
     # "stated": gamma0 in [1, 10] applied to both halves, eta/s in [1e-3, 0.2];
     # "paper": the paper's Riemann regime, tubes at rest, eta/s in [0.01, 0.2]
     mix = {} if args.serving_mix == "stated" else {"gamma_range": (1.0, 1.0), "eta_range": (0.01, 0.2)}
-    reqs = W.serving_requests(count=args.requests, **mix)
+    reqs = prepare(W.serving_requests(count=args.requests, **mix))
     lups = [q.n * q.steps for q in reqs]
     budget = int(args.serving_budget_gib * (1 << 30))
 
     # capacity: sustained batched rate (cell-updates per busy second) with a
     # saturating batch of the same distribution, steps capped so that no
     # single long request sets the duration
-    calib = W.serving_requests(count=max(args.requests // 4, 8), seed=W.SEED_BASE + 40, **mix)
+    calib = prepare(W.serving_requests(count=max(args.requests // 4, 8), seed=W.SEED_BASE + 40, **mix))
     for q in calib:
         q.steps = min(q.steps, 2048)
     with rlb.Server(common, budget, args.chunk) as srv:
@@ -262,7 +274,7 @@ def serving(args):
     sample_n, sample_rate = [], []
     for k in pick:
         q = reqs[k]
-        w = q.workload(precision=rlb.RLB_FP64, nu=nu)
+        w = q.workload(precision=rlb.RLB_FP64, nu=nu, dt=dt)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx = rlb.context_for_workload(w, precision=rlb.RLB_FP64)
@@ -283,7 +295,7 @@ def serving(args):
         "value": round(agg, 2), "unit": "MLUPS", "n_gpus": 1, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32-storage/f64-recovery", "data": "synthetic",
         "config": {"workload": "serving_shock_tubes_1d", "mix": args.serving_mix, "requests": len(reqs),
-                   "nu": nu,
+                   "nu": nu, "dt_over_dx": dt, "stabilised": bool(args.serving_stabilised),
                    "offered_load": args.load, "rate_per_s": round(rate, 3), "chunk_steps": args.chunk,
                    "arena_cells": int(sst.capacity_cells),
                    "cell_updates_requested": float(sum(lups))},
@@ -330,6 +342,9 @@ def main():
     ap.add_argument("--serving-budget-gib", type=float, default=16.0)
     ap.add_argument("--serving-nu", type=float, default=4.0)
     ap.add_argument("--serving-mix", default="stated", choices=["stated", "paper"])
+    ap.add_argument("--serving-stabilised", action="store_true",
+                    help="serve under the stabilised parameter set (nu = 4, alpha = 0.1, dt = 0.075) "
+                         "over the same physical run times")
     ap.add_argument("--baseline-sample", type=int, default=12)
     args = ap.parse_args()
     if args.gpus != 1:
