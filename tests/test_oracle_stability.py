@@ -38,6 +38,11 @@ scheme as read for uniform flows along a lattice axis (asserted below):
     cells long; the shortest wave is damped except in the Euler mode); for
     nu between about 3.2 and 7 the density part is stable for every
     |u| <= 0.99; nu = 9 is unstable again from |u| ~ 0.8.
+
+The basic model (exact streaming, explicit collision) has no limiter, so
+every Fourier mode of its step is pinned against the oracle; a uniform flow
+there grows from |u| ~ 0.5 (0.12 per step at u = 0.7), far faster than in
+the extended model, which is the paper's comparison in linear terms.
 """
 import math
 
@@ -326,3 +331,92 @@ def test_stabilised_colliding_slabs_run_clean(oracle_mod):
     c = w.nx // 2
     assert abs(eps[c - 8:c + 8].mean() / (3.0 * 529.998) - 1.0) < 1e-3
     assert n.max() < 100.0 and np.isfinite(eps).all()
+
+
+# --- the basic model (Sec. II): exact streaming, explicit collision --------
+
+def _basic_linear(O, nu, u):
+    q = 19
+    ux, uy, uz = _vel(u)
+    K = np.stack([O.moments(nu, np.eye(q)[i], basic=True)[0] for i in range(q)], 1)
+    U0 = O.moments(nu, O.feq(nu, 3.0, ux, uy, uz, basic=True), basic=True)[0]
+
+    def feq_of_U(U):
+        rc, fl = O.recover(U, 0.0, with_h=False)
+        assert rc == 0
+        return O.feq(nu, fl[0], fl[1], fl[2], fl[3], basic=True)
+
+    J = np.stack([_fd(feq_of_U, U0, k, 1e-5 * U0[0]) for k in range(4)], 1)
+    # d f^eq / d(eps, ux, uy, uz) at the uniform state (19 x 4)
+    dfe = np.stack([_fd(lambda v: O.feq(nu, v[0], v[1], v[2], v[3], basic=True), [3.0, ux, uy, uz], k, 1e-6)
+                    for k in range(4)], 1)
+    return K, J, dfe
+
+
+def _basic_matrix(O, nu, u, tau, theta, lin=None):
+    """One basic-model step on the mode exp(i theta x): explicit relaxation
+    f + omega (f^eq - f), omega = nu^2 / (sqrt 19 tau), then exact streaming
+    by one link, f_i(x) <- f_i(x - e_i)."""
+    K, J, _ = lin or _basic_linear(O, nu, u)
+    e = O.lattice(nu, basic=True)[0]
+    om = nu * nu / (math.sqrt(19.0) * tau)
+    S = np.diag(np.exp(-1j * theta * e[:, 0]))
+    return S @ ((1.0 - om) * np.eye(19) + om * J @ K)
+
+
+@pytest.mark.parametrize("u,tau,mode,steps,amp,grows", [
+    (0.7, 0.6, 8, 40, 1e-8, True),   # shortest wave: grows e^{0.12} per step
+    (0.7, 0.6, 3, 40, 1e-8, True),   # a longer wave (complex amplitude)
+    (0.3, 1.0, 5, 40, 1e-6, False),  # slow flow: damped
+])
+def test_basic_model_uniform_flow_follows_linear_theory(oracle_mod, u, tau, mode, steps, amp, grows):
+    """Exact streaming has no limiter, so every Fourier mode of a small
+    perturbation follows the linear matrix (16 cells, theta = 2 pi mode / 16)."""
+    O = oracle_mod
+    nx, nu = 16, 1.0
+    theta = 2.0 * math.pi * mode / nx
+    lin = _basic_linear(O, nu, u)
+    G = _basic_matrix(O, nu, u, tau, theta, lin)
+    x = np.arange(nx)
+    cfg = O.Config(nx=nx, nu=nu, dt=0.0, tau_mode=O.TAU_UNIFORM, tau=tau, bc=[O.BC_PERIODIC] * 6, basic=True)
+    o = O.Oracle(cfg)
+    # perturb eps and every velocity component (the growing modes of a flow
+    # along x include transverse ones, which an eps perturbation alone misses)
+    d = amp * np.array([3.0, 0.7, 0.5, 0.3])
+    c = np.cos(theta * x)
+    o.init(3.0 + d[0] * c, u + d[1] * c, d[2] * c, d[3] * c, None)
+    a = (lin[2] @ d).astype(complex)
+    a0 = np.abs(a).max()
+    proj = np.exp(-1j * theta * x) * (1.0 if mode == nx // 2 else 2.0) / nx
+    worst = 0.0
+    for _ in range(steps):
+        assert o.step(1) == 0
+        a = G @ a
+        meas = o.pops()[0] @ proj
+        worst = max(worst, float(np.abs(meas - a).max() / np.abs(a).max()))
+    gain = float(np.abs(a).max() / a0)
+    print(f"max rel. deviation from the linear prediction {worst:.1e}, gain {gain:.3g}")
+    assert worst < 1e-5, worst
+    assert (gain > 2.0) if grows else (gain < 1.0)
+
+
+def test_basic_model_is_far_less_stable_than_extended(oracle_mod):
+    """The paper's comparison (Sec. III: the basic model fails above beta ~
+    0.6, the extended one does not) in linear terms, at the comparison's
+    settings (basic: nu = 1, tau = 0.51, step sqrt(27/19); extended:
+    nu = 27^(1/4), alpha = 0.15, dt = 0.25, tau = 0.55): growth per unit time
+    of the fastest mode of a uniform flow."""
+    O = oracle_mod
+    t_basic = math.sqrt(27.0 / 19.0)
+
+    def basic(u):
+        lin = _basic_linear(O, 1.0, u)
+        return _growth(lambda t: _basic_matrix(O, 1.0, u, 0.51, t, lin)) / t_basic
+
+    def extended(u):
+        lin = _f_linear(O, NU0, u)
+        return _growth(lambda t: _f_matrix(O, NU0, u, 0.25, 0.55, 0.15, t, lin)) / 0.25
+
+    assert basic(0.3) < 1e-7 and extended(0.3) < 1e-7
+    assert basic(0.6) > 0.015 and extended(0.6) < 1e-4
+    assert basic(0.7) > 50.0 * extended(0.7)
