@@ -106,3 +106,47 @@ def test_density_part_follows_linear_theory(rlb, shape, axes, u, tau, steps, gro
     print(f"max rel. deviation from the linear prediction {worst:.1e}, gain {gain:.3g}")
     assert worst < 1e-6, worst
     assert (gain > 2.0) if grows else (gain < 1.0)
+
+
+@pytest.mark.parametrize("mode", [3, 8])
+def test_basic_model_follows_linear_theory(rlb, mode):
+    """The basic-model kernel (k_step_basic, FP64) on a uniform flow at
+    u = 0.7 with a small perturbation of eps and of every velocity component:
+    the Fourier amplitude of eps read back after every step follows the
+    basic model's linear matrix (the paper's beta ~ 0.6 limit: it grows)."""
+    import math as m
+    from oracle import oracle as O
+    from tests.test_oracle_stability import _basic_linear, _basic_matrix, _fd
+    nx, u, tau, amp, steps = 16, 0.7, 0.6, 1e-8, 40
+    theta = 2.0 * m.pi * mode / nx
+    lin = _basic_linear(O, 1.0, u)
+    K, J, dfe = lin
+    G = _basic_matrix(O, 1.0, u, tau, theta, lin)
+    U0 = O.moments(1.0, O.feq(1.0, 3.0, u, 0.0, 0.0, basic=True), basic=True)[0]
+    deps = np.array([_fd(lambda U: np.array([O.recover(U, 0.0, with_h=False)[1][0]]), U0, k, 1e-5 * U0[0])[0]
+                     for k in range(4)])
+    d = amp * np.array([3.0, 0.7, 0.5, 0.3])
+    x = np.arange(nx)
+    c = np.cos(theta * x).reshape(1, 1, nx)
+    w = W.Workload("basic_mode", nx, 1, 1, steps, precision=W.FP64, tau_mode=W.TAU_UNIFORM, tau=tau,
+                   nu=1.0, lattice=W.LATTICE_BASIC)
+    w.eps, w.ux, w.uy, w.uz = 3.0 + d[0] * c, u + d[1] * c, d[2] * c, d[3] * c
+    print(f"[gpu-case] basic model mode {mode} of {nx}, u = {u}, {steps} steps", flush=True)
+    proj = np.exp(-1j * theta * x) * (1.0 if mode == nx // 2 else 2.0) / nx
+    a = (dfe @ d).astype(complex)
+    a0 = abs(deps @ K @ a)
+    ctx = rlb.context_for_workload(w)
+    worst = 0.0
+    try:
+        for _ in range(steps):
+            ctx.rlb_step(1)
+            a = G @ a
+            meas = ctx.rlb_moments()[0].reshape(-1) @ proj
+            pred = deps @ K @ a
+            worst = max(worst, abs(meas - pred) / abs(pred))
+    finally:
+        ctx.close()
+    gain = abs(deps @ K @ a) / a0
+    print(f"max rel. deviation from the linear prediction {worst:.1e}, gain {gain:.3g}")
+    assert worst < 1e-5, worst
+    assert gain > 2.0
