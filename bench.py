@@ -37,16 +37,17 @@ def kernel_hash() -> str:
 
 
 def algorithmic_bytes_per_cell(precision: int, with_density: bool, collision: int, obstacle: bool,
-                               lattice: int = 0) -> int:
+                               lattice: int = 0, multi_d: bool = False) -> int:
     """Each population read once and written once; previous-step fields read
-    and written once (implicit mode of the extended model); obstacle mask
-    read once."""
+    and written once (implicit mode of the extended model: five FP64 values,
+    or five FP32 values in the compact form of the mixed-precision 2D/3D
+    step); obstacle mask read once."""
     e = 8 if precision == 0 else 4
     b = 2 * 19 * e
     if with_density:
         b += 2 * 19 * e
     if collision == 0 and lattice == 0:
-        b += 2 * 5 * 8
+        b += 2 * 5 * (4 if (precision != 0 and multi_d) else 8)
     if obstacle:
         b += 1
     return b
@@ -407,7 +408,7 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     mlups = w.ncell * args.steps / wall / 1e6
     bpc = algorithmic_bytes_per_cell(precision, w.with_density, w.collision, w.obstacle is not None,
-                                     w.lattice)
+                                     w.lattice, w.ny > 1 or w.nz > 1)
     # one launch reads and writes each cell's state once for `spl` steps
     bytes_launch = bpc * w.ncell
     achieved = bytes_launch / (kern_ms * spl * 1e-3) / 1e9

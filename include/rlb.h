@@ -25,7 +25,9 @@
  *   - The context owns all device memory (allocated in rlb_create, released
  *     in rlb_destroy).  Device memory per cell: 2 x 19 populations of f and
  *     (with density) of h in the storage precision (ping-pong), plus 5 FP64
- *     fields of the previous step and, with obstacles, 1 byte.
+ *     fields of the previous step (and, for the implicit mixed-precision
+ *     step of a 2D or 3D grid, 5 FP32 ones: the step keeps its history in
+ *     FP32) and, with obstacles, 1 byte.
  *   - Threading: one context per host thread at a time.  Contexts are
  *     independent.  Results are deterministic for a given configuration
  *     and device.

@@ -48,6 +48,7 @@ struct rlb_ctx {
   void* h[2] = {nullptr, nullptr};
   int cur = 0;
   double* hist = nullptr;
+  float* hist32 = nullptr;  // compact previous-step fields (see compact_history)
   uint8_t* obst = nullptr;
   double* face_states = nullptr;   // [6][5]
   unsigned long long* counters = nullptr;  // [0] bad step, [1] guard events, [2] moments flag
@@ -116,6 +117,13 @@ rlb_status validate(const rlb_config* c) {
   return RLB_OK;
 }
 
+// The implicit mixed-precision step of 2D and 3D grids of the extended model
+// keeps the previous-step fields in FP32 as (eps, gamma u, n) (StepParams::hist32).
+bool compact_history(const rlb_config* c) {
+  return c->precision != RLB_FP64 && (c->ny > 1 || c->nz > 1) && c->collision == RLB_COLL_IMPLICIT &&
+         c->lattice == RLB_LATTICE_EXTENDED;
+}
+
 uint64_t footprint(const rlb_config* c) {
   const uint64_t nc = static_cast<uint64_t>(c->nx) * c->ny * c->nz;
   const uint64_t ns = static_cast<uint64_t>(rlb::row_pitch(c->nx, c->ny)) * rlb::plane_rows(c->ny) * c->nz;
@@ -124,6 +132,7 @@ uint64_t footprint(const rlb_config* c) {
   uint64_t b = 2 * rlb::Q * ps * elem;            // f, ping-pong
   if (c->with_density) b += 2 * rlb::Q * ps * elem;
   b += 5 * ns * 8;                                // previous-step fields
+  if (compact_history(c)) b += 5 * ns * 4;        // and their FP32 form
   b += (nc + 255) / 256 * 5 * 8;                  // reduction partials
   b += 6 * 5 * 8 + 4 * 8 + 8 * 8;                 // face states, counters, sums
   return b;
@@ -135,6 +144,7 @@ void free_all(rlb_ctx* x) {
     if (x->h[k]) (void)hipFree(x->h[k]);
   }
   if (x->hist) (void)hipFree(x->hist);
+  if (x->hist32) (void)hipFree(x->hist32);
   if (x->obst) (void)hipFree(x->obst);
   if (x->face_states) (void)hipFree(x->face_states);
   if (x->counters) (void)hipFree(x->counters);
@@ -211,6 +221,7 @@ void fill_params(rlb_ctx* x) {
   for (int k = 0; k < 6; ++k) p.bc[k] = c.bc[k];
   fill_constants(c, p);
   p.hist = x->hist;
+  p.hist32 = x->hist32;
   p.obst = nullptr;
   p.cell0 = 0;
   p.range = x->ncell;
@@ -376,6 +387,8 @@ rlb_status rlb_create(const rlb_config* cfg, void* hip_stream, rlb_ctx** out) {
     if (st == RLB_OK && cfg->with_density) st = dalloc(&x->h[k], pop_bytes, "h");
   }
   if (st == RLB_OK) st = dalloc(&x->hist, 5 * sizeof(double) * x->nstore, "fields");
+  if (st == RLB_OK && compact_history(cfg))
+    st = dalloc(&x->hist32, 5 * sizeof(float) * x->nstore, "fields (FP32)");
   if (st == RLB_OK) st = dalloc(&x->face_states, 6 * 5 * sizeof(double), "face_states");
   if (st == RLB_OK) st = dalloc(&x->counters, 4 * sizeof(unsigned long long), "counters");
   if (st == RLB_OK) st = dalloc(&x->sums_partial, static_cast<size_t>(x->sums_blocks) * 5 * sizeof(double), "sums");

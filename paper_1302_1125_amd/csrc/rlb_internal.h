@@ -59,6 +59,10 @@ struct StepParams {
   const void* h_in;
   void* h_out;
   double* hist;            // [5][ncell]: eps, ux, uy, uz, n of the previous step
+  // [5][ncell] FP32: eps, gamma ux, gamma uy, gamma uz, n of the previous step.
+  // Used instead of hist by the implicit mixed-precision step of 2D and 3D grids
+  // (nullptr otherwise); hist then keeps the initial (obstacle) fields.
+  float* hist32;
   const uint8_t* obst;     // [ncell] or nullptr
   long long ncell;         // storage cells px * py * nz (pad cells included)
   long long pstride;       // elements per population array (population_stride)

@@ -5,7 +5,9 @@
 // h[i][cell] with cell = x + px (y + py z) (2D/3D rows and planes padded to
 // the 64 x 4 tiles, rlb_internal.h) and a per-population stride that leaves
 // six face slots after the cells; two copies (ping-pong).  The fields of the previous step hist[k][cell]
-// (FP64, k = eps, ux, uy, uz, n) are read and rewritten in place by their cell.
+// (FP64, k = eps, ux, uy, uz, n) are read and rewritten in place by their cell;
+// the implicit mixed-precision step of 2D/3D grids keeps them in FP32 as
+// hist32[k][cell] (k = eps, gamma ux, gamma uy, gamma uz, n) instead.
 //
 // One fused kernel per step, one thread per cell, one workgroup per tile
 // (64 x 4 cells in 2D/3D, 256 cells in 1D).  The thread loads the 38 centre
@@ -967,8 +969,30 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
     }
     return;
   } else {
-    const double pe = ldb_nt(h0, cdl), pux = ldb_nt(h1, cdl), puy = ldb_nt(h2, cdl),
-                 puz = ldb_nt(h3, cdl), pn = ldb_nt(h4, cdl);
+    // previous fields: FP64 (eps, u, n), or FP32 (eps, gamma u, n) in the
+    // compact form of the mixed-precision 2D/3D step, where gamma^2 =
+    // 1 + |gamma u|^2 has no cancellation at high speed
+    constexpr bool kCompact = std::is_same<T, float>::value && !SEG && ACT != 1;
+    double pe, pux, puy, puz, pn, pg2;
+    if constexpr (kCompact) {
+      const float* __restrict__ q = P.hist32;
+      const unsigned o = inside ? cl : 0u;
+      pe = ldb_nt(q, o);
+      const double gx = ldb_nt(q + NC, o), gy = ldb_nt(q + 2 * NC, o), gz = ldb_nt(q + 3 * NC, o);
+      pn = ldb_nt(q + 4 * NC, o);
+      pg2 = 1.0 + (gx * gx + gy * gy + gz * gz);
+      const double ig = 1.0 / sqrt(pg2);
+      pux = gx * ig;
+      puy = gy * ig;
+      puz = gz * ig;
+    } else {
+      pe = ldb_nt(h0, cdl);
+      pux = ldb_nt(h1, cdl);
+      puy = ldb_nt(h2, cdl);
+      puz = ldb_nt(h3, cdl);
+      pn = ldb_nt(h4, cdl);
+      pg2 = 1.0 / (1.0 - (pux * pux + puy * puy + puz * puz));
+    }
     // 1-2: moments and fields at time t.
     double E, Mx, My, Mz, N0;
     moments64<T, WH>(P, [&](auto I) { return fc[I]; }, [&](auto I) { return hc[I]; }, E, Mx, My,
@@ -982,7 +1006,6 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
     const double omega = P.omega_c / tau_of<T, WH>(P, F, tau_u, nu2e);
     const double inv1p = 1.0 / (1.0 + omega);
     const double src = omega * inv1p;
-    const double pg2 = 1.0 / (1.0 - (pux * pux + puy * puy + puz * puz));
     T Kt[10];
     {
       double K[10], Kp[10];
@@ -1001,12 +1024,21 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
       for (int k = 0; k < 10; ++k) Ht[k] = static_cast<T>(solid ? Hp[k] : src * (2.0 * H[k] - Hp[k]));
     }
     if (real) {
-      double* __restrict__ w0 = hist;
-      stb_nt(w0, cd, F.eps);
-      stb_nt(w0 + NC, cd, F.ux);
-      stb_nt(w0 + 2 * NC, cd, F.uy);
-      stb_nt(w0 + 3 * NC, cd, F.uz);
-      stb_nt(w0 + 4 * NC, cd, F.n);
+      if constexpr (kCompact) {
+        float* __restrict__ q = P.hist32;
+        stb_nt(q, cl, static_cast<float>(F.eps));
+        stb_nt(q + NC, cl, static_cast<float>(F.gam * F.ux));
+        stb_nt(q + 2 * NC, cl, static_cast<float>(F.gam * F.uy));
+        stb_nt(q + 3 * NC, cl, static_cast<float>(F.gam * F.uz));
+        stb_nt(q + 4 * NC, cl, static_cast<float>(F.n));
+      } else {
+        double* __restrict__ w0 = hist;
+        stb_nt(w0, cd, F.eps);
+        stb_nt(w0 + NC, cd, F.ux);
+        stb_nt(w0 + 2 * NC, cd, F.uy);
+        stb_nt(w0 + 3 * NC, cd, F.uz);
+        stb_nt(w0 + 4 * NC, cd, F.n);
+      }
     }
 
     // obstacle lanes keep only the equilibrium term (exact: 0 * finite + y)
@@ -1530,6 +1562,15 @@ __global__ __launch_bounds__(kBlock) void k_init(const StepParams P) {
     static_for<0, Q>([&](auto I) { h[I * S + c] = static_cast<T>(wprime<I>(P) * bracket<I>(H)); });
   } else {
     P.hist[4 * NC + c] = pow(eps / 3.0, 0.75);
+  }
+  if (P.hist32 != nullptr) {
+    // compact previous-step fields (eps, gamma u, n) in FP32
+    const double gam = sqrt(g2);
+    P.hist32[c] = static_cast<float>(eps);
+    P.hist32[NC + c] = static_cast<float>(gam * ux);
+    P.hist32[2 * NC + c] = static_cast<float>(gam * uy);
+    P.hist32[3 * NC + c] = static_cast<float>(gam * uz);
+    P.hist32[4 * NC + c] = static_cast<float>(P.hist[4 * NC + c]);
   }
 }
 

@@ -69,7 +69,13 @@ def test_host_side_validation_without_device():
     m = rlb.config_from(128, 64, 32, precision=rlb.RLB_MIXED, with_density=True)
     n = 128 * 64 * 32
     fp = rlb.rlb_footprint_bytes(m)
-    assert n * (4 * 19 * 4 + 5 * 8) <= fp <= n * (4 * 19 * 4 + 5 * 8) * 1.01 + 4096
+    # f and h (two copies each), the FP64 previous-step fields and their FP32
+    # form (implicit mixed-precision step of a 3D grid)
+    per_cell = 4 * 19 * 4 + 5 * 8 + 5 * 4
+    assert n * per_cell <= fp <= n * per_cell * 1.01 + 4096
+    eu = rlb.config_from(128, 64, 32, precision=rlb.RLB_MIXED, with_density=True,
+                         collision=rlb.RLB_COLL_EULER)
+    assert rlb.rlb_footprint_bytes(eu) == fp - n * 5 * 4
     bad = rlb.config_from(8, 1, 4)
     assert rlb.rlb_footprint_bytes(bad) == 0
 

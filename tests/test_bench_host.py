@@ -28,6 +28,9 @@ def test_more_than_one_gpu_is_refused():
     ((1, True, 1, True, 0), 305),    # Euler mode (no previous fields) + obstacle mask
     ((1, False, 0, True, 1), 153),   # basic model: f only, no previous fields, obstacle
     ((0, False, 0, False, 1), 304),  # basic model, FP64
+    ((1, True, 0, False, 0, True), 344),   # mixed 2D/3D: previous fields in FP32
+    ((0, True, 0, False, 0, True), 688),   # FP64 2D/3D: unchanged
+    ((1, True, 1, True, 0, True), 305),    # Euler mode: no previous fields
 ])
 def test_algorithmic_bytes_per_cell(args, expected):
     assert bench.algorithmic_bytes_per_cell(*args) == expected
