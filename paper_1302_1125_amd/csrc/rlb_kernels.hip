@@ -956,6 +956,11 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
     T Kt[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k) Kt[k] = static_cast<T>(K[k]);
+    // lanes past the grid end (staged tiles) store nothing here: no cell
+    // reads the pad cells.  (The implicit step below stores them to their own
+    // pad cells instead: predicating its interleaved stores cost 10% of the
+    // time of unpadded grids.)
+    if (!inside) return;
     static_for<0, Q>(
         [&](auto I) { stb_nt(fout + I * S, cbs, static_cast<T>(weight(I)) * bracket<I>(Kt)); });
     if constexpr (WH) {
