@@ -297,3 +297,26 @@ def test_uniform_moving_state_fixed_point(rlb):
     e, ux, uy, uz, n = ctx.rlb_moments()
     ctx.close()
     assert abs(e - 2.0).max() < 1e-5 and abs(ux - 0.5).max() < 1e-5 and abs(n - 1.5).max() < 1e-5
+
+
+@pytest.mark.parametrize("speed", [0.6, 0.9])
+def test_mixed_fast_smooth_flow_3d(rlb, speed):
+    """The mixed-precision 3D step at high speed, where its FP32 history
+    fields matter most: a smooth random state riding on a uniform flow of
+    |u| = speed along (2, 1, 1)/sqrt 6 (periodic 24x16x12, density on,
+    stabilised parameters so that the flow itself is linearly stable), 60
+    steps, against the FP64 oracle within the mixed-precision bounds."""
+    w = W.random_smooth_state(24, 16, 12, seed=31, with_density=True, umax=0.05,
+                              tau_mode=W.TAU_ETA_OVER_S, eta_over_s=0.05, **W.STABILISED)
+    d = np.array([2.0, 1.0, 1.0]) / math.sqrt(6.0)
+    ux, uy, uz = (w.ux + speed * d[0], w.uy + speed * d[1], w.uz + speed * d[2])
+    assert float(np.max(ux ** 2 + uy ** 2 + uz ** 2)) < 0.99
+    w.ux, w.uy, w.uz = ux, uy, uz
+    steps = 60
+    _case(f"mixed fast flow |u|={speed}", w, steps)
+    g, _ = _run_gpu(rlb, w, steps, precision=W.MIXED)
+    o, _ = _run_oracle(w, steps)
+    errs = field_errors(g, o)
+    print("mixed-precision rel. L2 errors:", errs)
+    for k, v in errs.items():
+        assert v <= MIXED_BOUNDS[k], (k, v, errs)
