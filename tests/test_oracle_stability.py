@@ -420,3 +420,28 @@ def test_basic_model_is_far_less_stable_than_extended(oracle_mod):
     assert basic(0.3) < 1e-7 and extended(0.3) < 1e-7
     assert basic(0.6) > 0.015 and extended(0.6) < 1e-4
     assert basic(0.7) > 50.0 * extended(0.7)
+
+
+@pytest.mark.parametrize("euler", [True, False])
+def test_stabilised_parameters_keep_the_riemann_plateau(euler):
+    """The stabilised set adds bulk viscosity, which broadens shocks but must
+    leave their jumps: the pressure-ratio-16 tube (outflow ends, t = 250)
+    keeps the exact ideal-fluid plateau, u* within 0.2% and p* within 0.5%."""
+    from oracle import riemann as R
+    from paper_1302_1125_amd import workloads as W
+    from tests._helpers import oracle_for
+    st = W.STABILISED
+    nx, ratio = 1600, 16.0
+    steps = int(round(250.0 / st["dt"]))
+    w = W.shock_tube_1d(nx=nx, steps=steps, T_left=ratio ** 0.25, T_right=1.0, alpha=st["alpha"],
+                        collision=int(euler), bc_ends=W.BC_OUTFLOW, nu=st["nu"], dt=st["dt"])
+    w = w.copy_with(tau_mode=W.TAU_UNIFORM, tau=1.0)
+    o = oracle_for(w)
+    assert o.step(steps) == 0
+    eps, ux = o.fields()[0].ravel(), o.fields()[1].ravel()
+    s = R.solve(ratio, 0.0, 1.0, 0.0)
+    t = steps * w.dt
+    lo = int(nx / 2 + t * (s.left_tail + 0.15 * (s.right_head - s.left_tail)))
+    hi = int(nx / 2 + t * (s.right_head - 0.15 * (s.right_head - s.left_tail)))
+    assert abs(np.median(ux[lo:hi]) / s.vstar - 1.0) < 2e-3
+    assert abs(np.median(eps[lo:hi] / 3.0) / s.pstar - 1.0) < 5e-3
