@@ -201,12 +201,16 @@ def test_colliding_slabs_fp64(rlb):
     _assert_fp64(errs)
 
 
-@pytest.mark.parametrize("which", ["shock_cloud", "blast", "tube", "shock_cloud_3d"])
+@pytest.mark.parametrize("which", ["shock_cloud", "blast", "tube", "shock_cloud_3d", "shock_cloud_3d_viscous"])
 def test_mixed_precision_errors(rlb, which):
     if which == "shock_cloud":
         w, steps = W.shock_cloud_2d(nx=256, ny=128, steps=20), 20
     elif which == "shock_cloud_3d":
         w, steps = W.shock_cloud_3d(nx=60, ny=30, nz=30, regime="weak"), 80
+    elif which == "shock_cloud_3d_viscous":
+        # implicit 3D step with an obstacle: the obstacle cells' prescribed
+        # fields come from the FP32 history of the mixed-precision step
+        w, steps = W.shock_cloud_3d(nx=60, ny=30, nz=30, regime="weak", viscous=True), 80
     elif which == "blast":
         w, steps = W.blast_wave_3d(n=32, steps=30), 30
     else:
