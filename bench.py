@@ -128,6 +128,7 @@ def record_traffic(args):
     except (OSError, ValueError):
         d = {}
     name = args.workload + ("_basic" if args.lattice == "basic" else "")
+    name += "_stabilised" if getattr(args, "stabilised", False) else ""
     d[f"{name}:{args.precision}"] = {
         "kernel_hash": kernel_hash(), "bytes_per_launch": round(fetch + write),
         "fetch_bytes": round(fetch), "write_bytes": round(write),
@@ -140,7 +141,8 @@ def record_traffic(args):
     print(json.dumps(d[f"{name}:{args.precision}"]))
 
 
-def cpu_baseline(workload: str, precision: int, budget_s: float, lattice: str = "extended"):
+def cpu_baseline(workload: str, precision: int, budget_s: float, lattice: str = "extended",
+                 stabilised: bool = False):
     """FP64 CPU oracle on a bounded sample of the same workload recipe."""
     from oracle import oracle as O
     from paper_1302_1125_amd import workloads as W
@@ -160,6 +162,9 @@ def cpu_baseline(workload: str, precision: int, budget_s: float, lattice: str = 
     if lattice == "basic":
         w = W.as_basic(w)
         sample += ", basic model"
+    if stabilised:
+        w = W.stabilised(w)
+        sample += ", stabilised parameters"
     cfg = O.Config(nx=w.nx, ny=w.ny, nz=w.nz, nu=w.nu, dt=w.dt, euler=(w.collision == 1),
                    tau_mode=w.tau_mode, tau=w.tau, eta_over_s=w.eta_over_s, alpha=w.alpha,
                    with_h=bool(w.with_density), bc=w.bc, face=w.face_states,
@@ -343,6 +348,9 @@ def main():
     ap.add_argument("--serving-budget-gib", type=float, default=16.0)
     ap.add_argument("--serving-nu", type=float, default=4.0)
     ap.add_argument("--serving-mix", default="stated", choices=["stated", "paper"])
+    ap.add_argument("--stabilised", action="store_true",
+                    help="run the grid workload under the stabilised parameter set (nu = 4, alpha = 0.1, "
+                         "dt = 0.075)")
     ap.add_argument("--serving-stabilised", action="store_true",
                     help="serve under the stabilised parameter set (nu = 4, alpha = 0.1, dt = 0.075) "
                          "over the same physical run times")
@@ -383,6 +391,11 @@ def main():
     if args.lattice == "basic":
         from paper_1302_1125_amd import workloads as W
         w = W.as_basic(w)
+    if args.stabilised:
+        # same recipe under the stabilised parameter set; the traffic counters
+        # were taken under the default set, so none is reported
+        from paper_1302_1125_amd import workloads as W
+        w = W.stabilised(w).copy_with(name=w.name + "_stabilised")
     # a dedicated stream (default priority): the library launches on it and
     # the timing events are recorded on it
     stream = torch.cuda.Stream()
@@ -419,7 +432,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(args.workload, precision, args.cpu_seconds, args.lattice)
+        cpu = cpu_baseline(args.workload, precision, args.cpu_seconds, args.lattice, args.stabilised)
 
     out = {
         "metric": "cell-updates/s (MLUPS) & % HBM roofline",
