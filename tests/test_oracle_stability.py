@@ -3,13 +3,14 @@ Neumann analysis built from the lattice tables and the equilibria (CPU only).
 
 A uniform state at rest or in motion is a fixed point of the scheme (pinned
 in test_oracle_step).  Perturb it along x by a small multiple of (-1)^x, the
-shortest wave (theta = pi).  Every population then has one-sided
-differences of opposite sign at every cell, so the minmod correction of the
-limited flux (Sec. II.B, Eqs. (46)-(49)) is exactly zero and the step acts on
-the perturbation as first-order upwind streaming.  Linearised about the
+shortest wave (theta = pi), or in 3D by (-1)^(x+y) or (-1)^(x+y+z).  Every
+population then has one-sided differences of opposite sign at every cell, so
+the minmod correction of the limited flux (Eqs. (47)-(53)) is exactly zero
+and the step acts on the perturbation as first-order upwind streaming.  Linearised about the
 uniform state, one step is a fixed matrix per Fourier mode theta:
   - streaming of population i with speed p_i = (c_0/c_t) xi_i^x:
-      S_i = 1 - |p_i| dt (1 - exp(-i theta sgn p_i));
+      S_i = 1 - |p_i| dt (1 - exp(-i theta sgn p_i))  (summed over the axes
+      for a wave vector theta);
   - bulk term (f only, i != 0, Eq. (55)): + kappa (2 cos theta - 2),
       kappa = (c_0 nu/c_t) alpha dt;
   - implicit update (Eq. (57)), omega = (c_0 nu/c_t) dt / tau:
