@@ -76,6 +76,12 @@ def test_host_side_validation_without_device():
     eu = rlb.config_from(128, 64, 32, precision=rlb.RLB_MIXED, with_density=True,
                          collision=rlb.RLB_COLL_EULER)
     assert rlb.rlb_footprint_bytes(eu) == fp - n * 5 * 4
+    # FP64 and 1D contexts keep the previous-step fields in FP64 only
+    f64 = rlb.config_from(128, 64, 32, precision=rlb.RLB_FP64, with_density=True)
+    assert n * (4 * 19 * 8 + 5 * 8) <= rlb.rlb_footprint_bytes(f64) <= n * (4 * 19 * 8 + 5 * 8) * 1.01 + 4096
+    one = rlb.config_from(1 << 16, precision=rlb.RLB_MIXED, with_density=True)
+    m1 = 1 << 16
+    assert m1 * (4 * 19 * 4 + 5 * 8) <= rlb.rlb_footprint_bytes(one) <= m1 * (4 * 19 * 4 + 5 * 8) * 1.01 + 4096
     bad = rlb.config_from(8, 1, 4)
     assert rlb.rlb_footprint_bytes(bad) == 0
 
