@@ -357,8 +357,9 @@ def main():
     ap.add_argument("--baseline-sample", type=int, default=12)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(domain decomposition is described in DESIGN.md, not implemented).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(a slab decomposition with one halo exchange per step is designed, not implemented).",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.record_traffic:
