@@ -176,6 +176,20 @@ rlb_status rlb_sync(rlb_ctx* ctx);
 rlb_status rlb_moments(rlb_ctx* ctx, double* eps, double* ux, double* uy,
                        double* uz, double* n);
 
+/* rlb_moments without any device allocation, for callers that cannot
+   allocate (code running between the captures of a HIP graph, tight serving
+   loops, harnesses that forbid hipMalloc).  Same fields, same kernel and the
+   same results as rlb_moments; the five FP64 fields are staged in a fixed
+   device array that the library holds on every GPU it runs on until the
+   process ends (40 MiB: 5 x 2^20 doubles) instead of a buffer allocated per
+   call.  Grids of more than 2^20 cells (nx*ny*nz) return RLB_E_INVALID_ARG
+   (use rlb_moments).  The array is shared by every context on one GPU and
+   keeps the last call's contents (every call overwrites the cells it reads
+   back); calls that overlap on one GPU, from different host threads or
+   streams, race on it and must be serialised by the caller. */
+rlb_status rlb_moments_noalloc(rlb_ctx* ctx, double* eps, double* ux, double* uy,
+                               double* uz, double* n);
+
 /* Steps one kernel launch advances: 1 for 2D/3D grids and the basic
    lattice; for 1D grids of the extended lattice the temporal-blocking depth
    (default 8, at most 16; the RLB_TB_STEPS environment variable read at

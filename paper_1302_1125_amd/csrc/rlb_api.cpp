@@ -56,6 +56,7 @@ struct rlb_ctx {
   double* sums_partial = nullptr;
   double* sums_out = nullptr;
   int sums_blocks = 0;
+  double* scratch = nullptr;  // this device's fixed read-back array (rlb::scratch_address)
   int tb_steps = 8;      // 1D: steps per temporally blocked launch (1: one step per launch)
   bool initialised = false;
   bool poisoned = false;
@@ -294,6 +295,21 @@ rlb_status read_counters(rlb_ctx* x) {
   return RLB_OK;
 }
 
+// Fields of the current populations through the device staging buffer
+// `stage` ([5][ncell] FP64), copied into the caller's host arrays; returns
+// after the copies are done.  Allocates nothing.
+hipError_t read_fields(rlb_ctx* x, double* stage, double* const dst[5]) {
+  rlb::StepParams p = x->base;
+  p.f_in = x->f[x->cur];
+  p.h_in = x->h[x->cur];
+  hipError_t e = rlb::launch_moments(p, x->fp64, x->cfg.with_density != 0, stage, x->counters + 2,
+                                     x->stream);
+  const size_t nb = sizeof(double) * x->ncell;
+  for (int k = 0; k < 5 && e == hipSuccess; ++k)
+    if (dst[k]) e = hipMemcpyAsync(dst[k], stage + k * x->ncell, nb, hipMemcpyDeviceToHost, x->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
+  return e;
+}
 }  // namespace
 
 extern "C" {
@@ -357,6 +373,13 @@ rlb_status rlb_create(const rlb_config* cfg, void* hip_stream, rlb_ctx** out) {
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
     delete x;
     return fail(RLB_E_DEVICE, std::string("built for gfx950, device is ") + prop.gcnArchName);
+  }
+  // the fixed read-back array of rlb_moments_noalloc on this device (looked
+  // up once per device, with the device current)
+  e = rlb::scratch_address(x->device, &x->scratch);
+  if (e != hipSuccess) {
+    delete x;
+    return hip_fail(e, "hipGetSymbolAddress(scratch)");
   }
   x->fp64 = cfg->precision == RLB_FP64;
   x->elem = x->fp64 ? 8 : 4;
@@ -559,6 +582,7 @@ rlb_status rlb_step(rlb_ctx* x, int64_t nsteps) {
   return rlb_sync(x);
 }
 
+
 rlb_status rlb_moments(rlb_ctx* x, double* eps, double* ux, double* uy, double* uz, double* n) {
   if (!x) return fail(RLB_E_INVALID_ARG, "ctx is NULL");
   if (!x->initialised) return fail(RLB_E_STATE, "rlb_init_fields has not been called");
@@ -567,17 +591,31 @@ rlb_status rlb_moments(rlb_ctx* x, double* eps, double* ux, double* uy, double* 
   double* out = nullptr;
   st = dalloc(&out, 5 * sizeof(double) * x->ncell, "moments");
   if (st != RLB_OK) return st;
-  rlb::StepParams p = x->base;
-  p.f_in = x->f[x->cur];
-  p.h_in = x->h[x->cur];
-  hipError_t e = rlb::launch_moments(p, x->fp64, x->cfg.with_density != 0, out, x->counters + 2, x->stream);
-  double* dst[5] = {eps, ux, uy, uz, n};
-  const size_t nb = sizeof(double) * x->ncell;
-  for (int k = 0; k < 5 && e == hipSuccess; ++k)
-    if (dst[k]) e = hipMemcpyAsync(dst[k], out + k * x->ncell, nb, hipMemcpyDeviceToHost, x->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
+  double* const dst[5] = {eps, ux, uy, uz, n};
+  const hipError_t e = read_fields(x, out, dst);
   (void)hipFree(out);
   if (e != hipSuccess) return hip_fail(e, "moments");
+  return RLB_OK;
+}
+
+rlb_status rlb_moments_noalloc(rlb_ctx* x, double* eps, double* ux, double* uy, double* uz,
+                               double* n) {
+  if (!x) return fail(RLB_E_INVALID_ARG, "ctx is NULL");
+  if (!x->initialised) return fail(RLB_E_STATE, "rlb_init_fields has not been called");
+  if (x->ncell > rlb::kScratchCells) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf,
+                  "rlb_moments_noalloc: grid of %lld cells exceeds the fixed read-back array "
+                  "(at most %lld cells); use rlb_moments",
+                  x->ncell, rlb::kScratchCells);
+    return fail(RLB_E_INVALID_ARG, buf);
+  }
+  if (!x->scratch) return fail(RLB_E_DEVICE, "fixed read-back array not resolved");
+  rlb_status st = set_device(x);
+  if (st != RLB_OK) return st;
+  double* const dst[5] = {eps, ux, uy, uz, n};
+  const hipError_t e = read_fields(x, x->scratch, dst);
+  if (e != hipSuccess) return hip_fail(e, "moments (no allocation)");
   return RLB_OK;
 }
 

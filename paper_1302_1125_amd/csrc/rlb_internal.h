@@ -152,6 +152,15 @@ hipError_t launch_step_tb(const StepParams& p, bool fp64, bool with_h, bool eule
 // Batched segment step over `grid` workgroups (p.tiles has >= grid entries).
 hipError_t launch_seg_step(const StepParams& p, bool fp64, bool with_h, bool euler, unsigned grid,
                            hipStream_t s);
+// Allocation-free field read-back: a fixed device array (one per GPU, held
+// until the process ends) that stages the five FP64 fields of k_moments for
+// grids of at most kScratchCells cells.  scratch_address() returns its device
+// address on `device`, which must be the current device; the first call per
+// device looks it up (hipGetSymbolAddress), later calls return the cached
+// pointer.  Only that pointer may be handed to kernels or copies.
+constexpr long long kScratchCells = 1ll << 20;
+constexpr int kScratchFields = 5;
+hipError_t scratch_address(int device, double** out);
 // Equilibria of a segment's two end states into its ghost cells (both copies).
 hipError_t launch_seg_ghosts(const StepParams& p, bool fp64, long long lo_cell, long long hi_cell,
                              const double* states_dev /*2 x 5*/, void* f0, void* f1, void* h0,

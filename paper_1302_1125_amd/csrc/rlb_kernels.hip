@@ -27,6 +27,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <type_traits>
 
 #include "rlb_internal.h"
@@ -1874,6 +1875,36 @@ hipError_t launch_sums(const StepParams& p, bool fp64, bool with_h, double* part
   else sums_p<float>(p, with_h, nblocks, partial, s);
   hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(kBlock), 0, s, partial, nblocks, out5);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch for the allocation-free field read-back
+// (rlb_moments_noalloc): the staging buffer of k_moments' five FP64 fields
+// for up to kScratchCells cells.  Every GPU holds its own copy for the life
+// of the process.  In host code the array's name is only a stand-in for the
+// symbol: kernels receive the device address that hipGetSymbolAddress
+// returns, looked up once per device with that device current.
+// ---------------------------------------------------------------------------
+namespace {
+static __device__ __align__(256) double scratch[kScratchFields * kScratchCells];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_address(int device, double** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
 }
 
 }  // namespace rlb

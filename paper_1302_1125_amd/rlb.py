@@ -32,7 +32,7 @@ RLB_LATTICE_EXTENDED, RLB_LATTICE_BASIC = 0, 1
 EXPORTED = [
     "rlb_config_default", "rlb_create", "rlb_init_fields", "rlb_step", "rlb_step_async",
     "rlb_sync", "rlb_moments", "rlb_stats_get", "rlb_destroy", "rlb_status_str",
-    "rlb_last_error", "rlb_footprint_bytes", "rlb_steps_per_launch",
+    "rlb_last_error", "rlb_footprint_bytes", "rlb_steps_per_launch", "rlb_moments_noalloc",
 ]
 
 
@@ -91,6 +91,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.rlb_step_async.argtypes = [vp, ctypes.c_int64]
     L.rlb_sync.argtypes = [vp]
     L.rlb_moments.argtypes = [vp, dp, dp, dp, dp, dp]
+    L.rlb_moments_noalloc.argtypes = [vp, dp, dp, dp, dp, dp]
     L.rlb_stats_get.argtypes = [vp, ctypes.POINTER(rlb_stats)]
     L.rlb_destroy.argtypes = [vp]
     L.rlb_destroy.restype = None
@@ -103,7 +104,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.rlb_steps_per_launch.argtypes = [vp]
     L.rlb_steps_per_launch.restype = ctypes.c_int32
     for name in ("rlb_config_default", "rlb_create", "rlb_init_fields", "rlb_step",
-                 "rlb_step_async", "rlb_sync", "rlb_moments", "rlb_stats_get"):
+                 "rlb_step_async", "rlb_sync", "rlb_moments", "rlb_moments_noalloc",
+                 "rlb_stats_get"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -225,6 +227,23 @@ class Context:
         out = [np.empty(self.ncell) for _ in range(5)]
         _check(self._L.rlb_moments(self._h, *[_dp(o) for o in out]))
         return [o.reshape(self.shape) for o in out]
+
+    def rlb_moments_noalloc(self, out=None):
+        """rlb_moments through the library's fixed device read-back array (no
+        device allocation; grids of at most 2^20 cells).  `out`: optional five
+        float64 host arrays of ncell elements to fill (else new ones)."""
+        if out is None:
+            out = [np.empty(self.ncell) for _ in range(5)]
+        for o in out:
+            if o.dtype != np.float64 or o.size != self.ncell or not o.flags.c_contiguous:
+                raise ValueError("outputs: five contiguous float64 arrays of ncell elements")
+        _check(self._L.rlb_moments_noalloc(self._h, *[_dp(o) for o in out]))
+        return [o.reshape(self.shape) for o in out]
+
+    def status_of_moments_noalloc(self) -> int:
+        """rlb_moments_noalloc returning the raw status (outputs discarded)."""
+        out = [np.empty(self.ncell) for _ in range(5)]
+        return int(self._L.rlb_moments_noalloc(self._h, *[_dp(o) for o in out]))
 
     def rlb_stats_get(self) -> rlb_stats:
         s = rlb_stats()
