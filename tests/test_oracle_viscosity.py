@@ -27,15 +27,22 @@ import pytest
 from oracle import oracle as O
 
 
-def _diffusivity(basic, nu, tau, nx=256, steps=600, dt=0.25, every=5):
-    """Decay rate of the shear mode / k^2, in dx^2 per unit time."""
+def _diffusivity(basic, nu, tau, nx=256, steps=600, dt=0.25, every=5, eta_over_s=None,
+                 eps=3.0, n=None):
+    """Decay rate of the shear mode / k^2, in dx^2 per unit time.  With
+    eta_over_s the relaxation time comes from the oracle's eta/s mode (the
+    density distribution carries n, so lambda = n / T^3 may differ from 1)."""
     x = np.arange(nx)
     mode = np.sin(2 * np.pi * (x + 0.5) / nx)
     z = np.zeros(nx)
-    cfg = O.Config(nx=nx, nu=nu, dt=0.0 if basic else dt, tau_mode=O.TAU_UNIFORM, tau=tau,
-                   bc=[O.BC_PERIODIC] * 6, basic=basic)
+    if eta_over_s is None:
+        cfg = O.Config(nx=nx, nu=nu, dt=0.0 if basic else dt, tau_mode=O.TAU_UNIFORM, tau=tau,
+                       bc=[O.BC_PERIODIC] * 6, basic=basic)
+    else:
+        cfg = O.Config(nx=nx, nu=nu, dt=dt, tau_mode=O.TAU_ETA_OVER_S, eta_over_s=eta_over_s,
+                       with_h=n is not None, bc=[O.BC_PERIODIC] * 6)
     o = O.Oracle(cfg)
-    o.init(np.full(nx, 3.0), z, 1e-4 * mode, z)
+    o.init(np.full(nx, eps), z, 1e-4 * mode, z, None if n is None else np.full(nx, float(n)))
     step_t = math.sqrt(27.0 / 19.0) if basic else dt
     ts, amps = [], []
     for s in range(every, steps + 1, every):
@@ -60,4 +67,41 @@ def test_basic_model_shear_viscosity(nu, tau):
 def test_extended_model_shear_viscosity(tau):
     nu = 27.0 ** 0.25
     vis, _ = _diffusivity(False, nu, tau, steps=3000, every=25)
+    assert abs(vis / (4.0 / math.sqrt(27.0) * tau / nu ** 2) - 1.0) < 0.015
+
+
+def _tau_eq41(nu, eta_over_s, eps, n):
+    """Eq. (41) solved for tau, eta = (eps + p)(tau - 1/2)/nu^2 with
+    eta = (eta/s) s and the entropy density of Sec. III, s = 4n - n ln lambda,
+    lambda = n / n_eq, n_eq = T^3 (lattice units, d_G / pi^2 = 1), p = n T."""
+    p = eps / 3.0
+    T = p / n
+    lam = n / T ** 3
+    s = 4.0 * n - n * math.log(lam)
+    return 0.5 + nu * nu * eta_over_s * s / (eps + p)
+
+
+@pytest.mark.parametrize("eps,n,eta_over_s", [(3.0, 2.0, 0.157), (3.0, 0.5, 0.157), (12.0, 1.0, 0.3)])
+def test_eta_over_s_mode_realises_eq41_tau(eps, n, eta_over_s):
+    """The eta/s mode on a uniform state with lambda = n/T^3 = 16, 1/16 and
+    1/64 (the ln lambda term of the entropy enters with both signs): the
+    measured shear diffusivity is (4/sqrt 27) tau / nu^2 with tau from
+    Eq. (41) and the Sec. III entropy, as for a uniform tau.  A wrong sign
+    of ln lambda, a missing nu^2 or a wrong (eps + p) changes tau by 20% or
+    more at these states."""
+    nu = 27.0 ** 0.25
+    tau = _tau_eq41(nu, eta_over_s, eps, n)
+    assert 0.8 < tau < 1.6
+    vis, _ = _diffusivity(False, nu, None, steps=3000, every=25, eta_over_s=eta_over_s,
+                          eps=eps, n=n)
+    assert abs(vis / (4.0 / math.sqrt(27.0) * tau / nu ** 2) - 1.0) < 0.015
+
+
+def test_eta_over_s_mode_without_density_uses_lambda_one():
+    """Without the density distribution n = T^3 (lambda = 1), so
+    tau = 1/2 + nu^2 (eta/s) / T with T = (eps/3)^(1/4)."""
+    nu, eos, eps = 27.0 ** 0.25, 0.1, 48.0
+    T = (eps / 3.0) ** 0.25
+    tau = 0.5 + nu * nu * eos / T
+    vis, _ = _diffusivity(False, nu, None, steps=3000, every=25, eta_over_s=eos, eps=eps, n=None)
     assert abs(vis / (4.0 / math.sqrt(27.0) * tau / nu ** 2) - 1.0) < 0.015
