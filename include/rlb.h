@@ -80,7 +80,12 @@ typedef struct {
                            RLB_TAU_ETA_OVER_S: per cell from Eq. (41),
                            tau = 1/2 + nu^2 (eta/s) s/(eps+p), with
                            s = n (4 - ln(n/T^3)), T = p/n (lattice units,
-                           d_G/pi^2 = 1); without density n = T^3.        */
+                           d_G/pi^2 = 1); without density n = T^3.
+                           The extended scheme's shear viscosity is
+                           (4/sqrt 27) tau (eps+p)/nu^2 (Chapman-Enskog
+                           with the moment-exact equilibrium), so this
+                           mode realises 4/sqrt(27) = 0.77 of the given
+                           eta/s.                                          */
   int32_t with_density; /* 1: carry the density distribution h (Eq. (58)) */
   double nu;            /* nu = c/c_s (Sec. II); > 0                        */
   double dt_over_dx;    /* time step; (0, 0.5]                              */
@@ -133,8 +138,12 @@ typedef struct {
    guard_efloor = 1e-10, extended lattice. */
 rlb_status rlb_config_default(rlb_config* cfg);
 
-/* Validate cfg, allocate device memory on the current HIP device and
-   compute the fixed-face equilibria.  hip_stream: a hipStream_t to run on
+/* Set up one run of the extended model (Sec. II.A) for the problem
+   statement of the paper's Sec. III set-ups: lattice (nu), time step,
+   viscosity (tau or eta/s, Eq. (41)), bulk constant alpha (Eq. (55)),
+   boundaries (fixed inlet states, open faces).  Validate cfg, allocate
+   device memory on the current HIP device and compute the fixed-face
+   equilibria (Eq. (36) reading, Eq. (58)).  hip_stream: a hipStream_t to run on
    (e.g. torch's current stream), or NULL for a stream the context creates
    and owns.  On error *out is NULL and nothing is allocated. */
 rlb_status rlb_create(const rlb_config* cfg, void* hip_stream, rlb_ctx** out);
@@ -153,8 +162,12 @@ rlb_status rlb_init_fields(rlb_ctx* ctx, const double* eps, const double* ux,
                            const double* uy, const double* uz, const double* n,
                            const uint8_t* obstacle);
 
-/* Advance nsteps >= 0 updates (one fused kernel launch per update on the
-   context's stream), then synchronise once.  If a step's recovery met a
+/* Advance nsteps >= 0 updates of Eq. (57) (moments, recovery with
+   eps = 3p, equilibria, minmod-limited streaming of Eqs. (47)-(53), bulk
+   term of Eqs. (54)-(55), implicit collision; Euler mode: f := f^eq of the
+   post-streaming moments, Sec. III) -- one fused kernel launch per update
+   on the context's stream (1D grids: several updates per launch, see
+   rlb_steps_per_launch) -- then synchronise once.  If a step's recovery met a
    non-obstacle cell with T^{00} <= 0, |T^{0a}| >= T^{00}, N^0 <= 0 (with
    density) or a non-finite value, returns RLB_E_INADMISSIBLE; rlb_stats
    reports the first such step and later calls return RLB_E_STATE until
@@ -171,7 +184,8 @@ rlb_status rlb_step_async(rlb_ctx* ctx, int64_t nsteps);
 rlb_status rlb_sync(rlb_ctx* ctx);
 
 /* Fields of the current populations: eps, u (and n) recovered in FP64 as
-   in step 2.  Any output pointer may be NULL (skipped).  n without density
+   in step 2, from the moments T^{00}, T^{0a} of f (Eq. (36)) and N^0 of h
+   with eps = 3p (Eq. (38)).  Any output pointer may be NULL (skipped).  n without density
    is (eps/3)^(3/4).  Cells whose moments are inadmissible get NaN. */
 rlb_status rlb_moments(rlb_ctx* ctx, double* eps, double* ux, double* uy,
                        double* uz, double* n);

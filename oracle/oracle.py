@@ -76,6 +76,8 @@ def _load():
     L.orc_guard_events.argtypes = [ctypes.c_void_p]
     L.orc_guard_events.restype = ctypes.c_int64
     L.orc_num_threads.restype = ctypes.c_int
+    L.orc_set_num_threads.argtypes = [ctypes.c_int]
+    L.orc_set_num_threads.restype = None
     _lib = L
     return L
 
@@ -239,3 +241,8 @@ class Oracle:
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's later parallel regions (timing only)."""
+    _load().orc_set_num_threads(int(n))

@@ -854,3 +854,13 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads later parallel regions use (timing of the oracle at one thread and
+   at all cores); no effect on results. */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

@@ -82,5 +82,6 @@ void orc_set_pops(orc_state* S, const double* f, const double* h /*nullable*/,
 void orc_get_hist(const orc_state* S, double* hist /*5 x cells*/);
 int64_t orc_guard_events(const orc_state* S);
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 
 #endif

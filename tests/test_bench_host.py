@@ -22,7 +22,21 @@ def test_more_than_one_gpu_is_refused():
 
 
 @pytest.mark.parametrize("args,expected", [
-    ((1, True, 0, False, 0), 384),   # mixed, density, implicit: 2*19*4 * 2 + 2*5*8
+    ((1, True, 0, 0), 384),    # mixed, density, implicit: 2*19*4 * 2 + 2*5*8
+    ((0, True, 0, 0), 688),    # FP64 with density
+    ((1, False, 0, 0), 216),   # mixed, no density: 152 + 2*4*8
+    ((0, False, 0, 0), 368),   # FP64, no density
+    ((1, True, 1, 0), 304),    # Euler mode: no previous fields
+    ((1, False, 0, 1), 152),   # basic model: f only, no previous fields
+    ((0, False, 0, 1), 304),   # basic model, FP64
+])
+def test_algorithmic_bytes_per_cell(args, expected):
+    """The per-cell figures of the measurement plan (384 / 216 / 688 / 368 B)."""
+    assert bench.algorithmic_bytes_per_cell(*args) == expected
+
+
+@pytest.mark.parametrize("args,expected", [
+    ((1, True, 0, False, 0), 384),   # mixed 1D, density, implicit: FP64 previous fields
     ((0, True, 0, False, 0), 688),   # FP64
     ((1, False, 0, False, 0), 232),  # mixed, no density: 152 + 80
     ((1, True, 1, True, 0), 305),    # Euler mode (no previous fields) + obstacle mask
@@ -32,8 +46,8 @@ def test_more_than_one_gpu_is_refused():
     ((0, True, 0, False, 0, True), 688),   # FP64 2D/3D: unchanged
     ((1, True, 1, True, 0, True), 305),    # Euler mode: no previous fields
 ])
-def test_algorithmic_bytes_per_cell(args, expected):
-    assert bench.algorithmic_bytes_per_cell(*args) == expected
+def test_stored_bytes_per_cell(args, expected):
+    assert bench.stored_bytes_per_cell(*args) == expected
 
 
 def _csv(path, counter, rows):
