@@ -83,6 +83,11 @@ struct StepParams {
   int zslab;
   long long ntiles;        // tiles in the grid
   long long tiles_per_xcd; // tiles assigned to each XCD (grid = 8 * this)
+  // z-marching step of 3D mixed-precision grids (k_step_zm): planes per run
+  // (0: off), workgroups (columns x runs) in all and per XCD
+  int zm_len;
+  long long zm_total;
+  long long zm_per_xcd;
   int bc[6];
   // lattice and run constants (FP64)
   double a_scale;   // nu^2 / 27: equilibrium amplitude A = a_scale * eps
@@ -152,6 +157,9 @@ hipError_t launch_step_tb(const StepParams& p, bool fp64, bool with_h, bool eule
 // Batched segment step over `grid` workgroups (p.tiles has >= grid entries).
 hipError_t launch_seg_step(const StepParams& p, bool fp64, bool with_h, bool euler, unsigned grid,
                            hipStream_t s);
+// Largest population stride (elements) of the z-marching step: ten FP32
+// arrays of one descriptor group stay below 2^32 bytes.
+constexpr long long kZmMaxStride = (1ll << 32) / (10 * 4) - 64;
 // Allocation-free field read-back: a fixed device array (one per GPU, held
 // until the process ends) that stages the five FP64 fields of k_moments for
 // grids of at most kScratchCells cells.  scratch_address() returns its device

@@ -458,6 +458,15 @@ __device__ __forceinline__ void make_nbr_stg(const StepParams& P, int x, int y, 
   }
 }
 
+// Workgroup barrier that orders LDS accesses only: the wave's outstanding
+// global loads and stores stay in flight across it (a full __syncthreads()
+// fence waits for all of them).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Fill the LDS tiles of populations [S0, S1) (f in slots 0.., h after them):
 // halo loads first, then (after `sync_before`: the previous stage's reads are
 // done) the centre row, halo row and halo columns, then a barrier.
@@ -482,7 +491,7 @@ __device__ __forceinline__ void stage_fill(T (*L)[kLH][kLW], const T* __restrict
       if constexpr (WH && vcomp(I, 0) != 0) vxh[k] = ldb(hin + I * S, N.hx);
     });
   }
-  if (sync_before) __syncthreads();
+  if (sync_before) lds_barrier();
   const int hrow = w < 2 ? w : kTY + w;
   const int hcol = lane < 2 ? lane : 64 + lane;
   static_for<0, NP>([&](auto k) {
@@ -499,7 +508,7 @@ __device__ __forceinline__ void stage_fill(T (*L)[kLH][kLW], const T* __restrict
       if constexpr (WH && vcomp(I, 0) != 0) L[NP + k][2 + w][hcol] = vxh[k];
     });
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // Star stencil of one population: per active axis the values the limited
@@ -1124,6 +1133,489 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
 }
 
 // ---------------------------------------------------------------------------
+// z-marching step of 3D grids (mixed precision, implicit update).  A
+// workgroup owns one 64 x 4 column of the grid and walks a run of zm_len
+// z-planes through it.  Each thread keeps, in registers, the z-window of
+// the arrays whose stencil reaches along z: the 10 populations with
+// e^z != 0 of f and of h (flux, planes z-2..z+1 for e^z > 0, z-1..z+2 for
+// e^z < 0) and the 8 populations of f with e^z = 0, i != 0 (bulk term,
+// planes z-1..z+1).  Moving to the next plane shifts the windows and loads
+// one new plane per array, so every population value is read from HBM once
+// per step (plus the first planes of a run); the loads of a plane are in
+// flight while the previous one computes.  x and y neighbours come from
+// the LDS-staged tiles as in k_step.  The per-cell arithmetic is k_step's,
+// in the same order.
+// ---------------------------------------------------------------------------
+
+// Window slot of population i: populations with e^z != 0 (flux along z)
+constexpr int zf_index(int i) {
+  return (i == 5 || i == 6) ? i - 5 : (i >= 11 ? i - 9 : -1);
+}
+// populations of f with e^z == 0, i != 0 (bulk term along z)
+constexpr int zl_index(int i) {
+  return (i >= 1 && i <= 4) ? i - 1 : ((i >= 7 && i <= 10) ? i - 3 : -1);
+}
+// populations of h with e^z == 0 (no z stencil)
+constexpr int ho_index(int i) {
+  return (i <= 4) ? i : ((i >= 7 && i <= 10) ? i - 2 : -1);
+}
+// window position of plane z (the centre) for a flux population
+constexpr int zf_centre(int i) { return vcomp(i, 2) > 0 ? 2 : 1; }
+
+#ifndef RLB_ZM_OCC
+#define RLB_ZM_OCC 2
+#endif
+
+// Plane q (uniform across the workgroup) under the z boundary condition:
+// either a plane index (periodic wrap, outflow clamp) or the FIXED face slot.
+struct ZPlane {
+  bool slot;
+  unsigned off;  // slot: byte offset of the face slot; else: the plane index
+};
+__device__ __forceinline__ ZPlane zplane(const StepParams& P, int q, unsigned esz) {
+  if (q >= 0 && q < P.nz) return {false, static_cast<unsigned>(q)};
+  const int side = q < 0 ? 0 : 1;
+  const int b = P.bc[4 + side];
+  if (b == kBcFixed) return {true, static_cast<unsigned>(P.ncell + 4 + side) * esz};
+  return {false, static_cast<unsigned>(b == kBcPeriodic ? (q < 0 ? q + P.nz : q - P.nz)
+                                                       : (q < 0 ? 0 : P.nz - 1))};
+}
+// Byte offset of a lane's column at plane zp: xy is the column's offset at
+// plane 0 and step its plane pitch in bytes (0 for a lane whose column is a
+// face slot of an x or y face: every plane reads that slot).
+__device__ __forceinline__ unsigned zcol(unsigned xy, unsigned step, ZPlane zp) {
+  return zp.slot ? zp.off : xy + zp.off * step;
+}
+
+// x and y part of the stencil of population I from the LDS tile L.
+template <typename T, int I, bool LAP>
+__device__ __forceinline__ void gather_xy_lds(const T (*L)[kLW], Sten<T>& s) {
+  const int r = 2 + (static_cast<int>(threadIdx.x) >> 6);
+  const int c = 2 + static_cast<int>(__lane_id());
+  constexpr int ex = vcomp(I, 0), ey = vcomp(I, 1);
+  if constexpr (ex > 0) {
+    s.v[0][0] = L[r][c - 2];
+    s.v[0][1] = L[r][c - 1];
+    s.v[0][2] = L[r][c + 1];
+  } else if constexpr (ex < 0) {
+    s.v[0][0] = L[r][c - 1];
+    s.v[0][1] = L[r][c + 1];
+    s.v[0][2] = L[r][c + 2];
+  } else if constexpr (LAP) {
+    s.v[0][0] = L[r][c - 1];
+    s.v[0][1] = L[r][c + 1];
+  }
+  if constexpr (ey > 0) {
+    s.v[1][0] = L[r - 2][c];
+    s.v[1][1] = L[r - 1][c];
+    s.v[1][2] = L[r + 1][c];
+  } else if constexpr (ey < 0) {
+    s.v[1][0] = L[r - 1][c];
+    s.v[1][1] = L[r + 1][c];
+    s.v[1][2] = L[r + 2][c];
+  } else if constexpr (LAP) {
+    s.v[1][0] = L[r - 1][c];
+    s.v[1][1] = L[r + 1][c];
+  }
+}
+
+// z part of the stencil of a flux population from its window W (planes
+// z-2..z+1 for e^z > 0, z-1..z+2 for e^z < 0), in the layout of gather().
+template <typename T, int I>
+__device__ __forceinline__ void zsten_flux(const T* W, Sten<T>& s) {
+  if constexpr (vcomp(I, 2) > 0) {
+    s.v[2][0] = W[0];
+    s.v[2][1] = W[1];
+    s.v[2][2] = W[3];
+  } else {
+    s.v[2][0] = W[0];
+    s.v[2][1] = W[2];
+    s.v[2][2] = W[3];
+  }
+}
+
+// Raw buffer access to the FP32 arrays of the z-marching step.  The 19
+// population arrays of one distribution are addressed through two buffer
+// descriptors (populations [0, 10) and [10, 19)); an access gives the
+// array's offset within its group as the scalar offset and the lane's byte
+// offset in the array as the vector offset.  No per-lane 64-bit address
+// arithmetic is needed and the descriptors stay in scalar registers for the
+// whole kernel.  A group spans at most 10 arrays, below 2^32 bytes for
+// population strides up to kZmMaxStride (rlb_internal.h; checked on the host).
+constexpr int kZmGroups = 2;
+constexpr int zm_grp(int i) { return i < 10 ? 0 : 1; }
+constexpr int zm_grp_first(int g) { return g == 0 ? 0 : 10; }
+struct PopBuf {
+  __amdgpu_buffer_rsrc_t g[kZmGroups];
+};
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const float* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, -1, 0x00020000);
+}
+__device__ __forceinline__ PopBuf pop_buf(const float* base, long long stride) {
+  PopBuf b;
+#pragma unroll
+  for (int k = 0; k < kZmGroups; ++k) b.g[k] = buf_rsrc(base + zm_grp_first(k) * stride);
+  return b;
+}
+// aux 2: non-temporal (data touched once per step)
+template <int I, int AUX = 0>
+__device__ __forceinline__ float pld(const PopBuf& b, unsigned off, unsigned sb) {
+  constexpr int g = zm_grp(I);
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_raw_buffer_load_b32(b.g[g], off, (I - zm_grp_first(g)) * sb, AUX));
+}
+template <int I, int AUX = 0>
+__device__ __forceinline__ void pst(const PopBuf& b, unsigned off, unsigned sb, float v) {
+  constexpr int g = zm_grp(I);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), b.g[g], off,
+                                        (I - zm_grp_first(g)) * sb, AUX);
+}
+constexpr int kNT = RLB_STREAMING ? 2 : 0;
+#ifndef RLB_ZM_STAGES
+#define RLB_ZM_STAGES 2
+#endif
+// populations staged through LDS together (f and h) in the z-marching step
+constexpr int kZmPops = (Q + RLB_ZM_STAGES - 1) / RLB_ZM_STAGES;
+
+template <typename T, bool WH>
+__global__ __launch_bounds__(kBlock, RLB_ZM_OCC) void k_step_zm(
+    const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ hin,
+    T* __restrict__ hout, double* __restrict__ hist, const uint8_t* __restrict__ obst,
+    const StepParams P) {
+  static_assert(std::is_same<T, float>::value, "the z-marching step stores FP32 populations");
+  constexpr int ACT = 7;
+  const unsigned esz = static_cast<unsigned>(sizeof(T));
+  // column and z-run of this workgroup: XCD k takes the k-th contiguous part
+  // of the (run, tile row, tile column) order
+  const long long g = static_cast<long long>(blockIdx.x % kXcds) * P.zm_per_xcd + blockIdx.x / kXcds;
+  if (g >= P.zm_total) return;  // the whole workgroup
+  const int tpp = P.ntx * P.nty;
+  const int run = static_cast<int>(g / tpp);
+  const int rem = static_cast<int>(g % tpp);
+  const int ty = rem / P.ntx, tx = rem % P.ntx;
+  const int zb = run * P.zm_len;
+  const int ze = zb + P.zm_len < P.nz ? zb + P.zm_len : P.nz;
+  const int lane = static_cast<int>(__lane_id());
+  // wavefront index, uniform (the LDS destinations of the loads into LDS
+  // must be scalar)
+  const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+  const int x = tx * 64 + lane, y = ty * kTY + wv;
+  const bool inside = x < P.nx && y < P.ny;
+  const unsigned plane_bytes = static_cast<unsigned>(P.px) * static_cast<unsigned>(P.py) * esz;
+  const long long NC = P.ncell;
+  // offsets at plane 0 (face slots of x or y faces are the same for every
+  // plane: their plane pitch is 0): the lane's value (boundary-mapped past
+  // the x or y end), its halo row and halo column, its own storage cell
+  const int pxc = x < P.nx + 1 ? x : P.nx + 1;
+  const int pyc = y < P.ny + 1 ? y : P.ny + 1;
+  const long long c0 = map_xy(P, pxc, pyc, 0);
+  const unsigned cxy = static_cast<unsigned>(c0) * esz;
+  const unsigned cst = c0 >= NC ? 0u : plane_bytes;
+  int hy = ty * kTY - 2 + (wv < 2 ? wv : kTY + wv);
+  hy = hy < P.ny + 1 ? hy : P.ny + 1;
+  const long long r0 = map_xy(P, pxc, hy, 0);
+  const unsigned rxy = static_cast<unsigned>(r0) * esz;
+  const unsigned rst = r0 >= NC ? 0u : plane_bytes;
+  const unsigned sxy = static_cast<unsigned>(x + static_cast<long long>(P.px) * y) * esz;
+  int hxp = lane < 2 ? tx * 64 - 2 + lane : tx * 64 + 62 + lane;
+  hxp = hxp < P.nx + 1 ? hxp : P.nx + 1;
+  const long long x0 = lane < 4 ? map_xy(P, hxp, pyc, 0) : c0;
+  const unsigned xxy = static_cast<unsigned>(x0) * esz;
+  const unsigned xst = x0 >= NC ? 0u : plane_bytes;
+
+  unsigned long long* bad_ptr = P.bad_step;
+  unsigned long long* guard_ptr = P.guard_count;
+  const long long step_idx = P.step_index;
+  const double kappa_d = P.kappa, nu2e = P.nu2_etas, tau_u = P.tau;
+  const T dtv = static_cast<T>(P.dtv);
+  constexpr T NA2 = T(2 * n_axes<ACT>());
+  const T wp[3] = {static_cast<T>(P.wp0), static_cast<T>(P.wp1), static_cast<T>(P.wp2)};
+  // LDS tiles of one stage: kZmPops populations of f, then of h
+  constexpr int NPS = kZmPops;
+  __shared__ T lds[(WH ? 2 : 1) * NPS][kLH][kLW];
+  // buffer descriptors: populations (in, out) and previous-step fields
+  const unsigned sb = static_cast<unsigned>(P.pstride) * esz;   // array pitch in bytes
+  const PopBuf Fi = pop_buf(fin, P.pstride), Fo = pop_buf(fout, P.pstride);
+  const PopBuf Hi = pop_buf(hin, P.pstride), Ho = pop_buf(hout, P.pstride);
+  PopBuf Qh;  // previous-step fields 0..4: one group (5 NC FP32 values)
+  Qh.g[0] = buf_rsrc(P.hist32);
+  const unsigned qb = static_cast<unsigned>(NC) * 4u;
+
+  // z-windows
+  T wf[10][4];
+  T wl[8][3];
+  T f0c;
+  T wh[WH ? 10 : 1][4];
+  T ho[WH ? 9 : 1];
+  auto fcen = [&](auto I) -> T {
+    constexpr int i = I;
+    if constexpr (i == 0) return f0c;
+    else if constexpr (zf_index(i) >= 0) return wf[zf_index(i)][zf_centre(i)];
+    else return wl[zl_index(i)][1];
+  };
+  auto hcen = [&](auto I) -> T {
+    constexpr int i = I;
+    if constexpr (zf_index(i) >= 0) return wh[zf_index(i)][zf_centre(i)];
+    else return ho[ho_index(i)];
+  };
+  // centres without a z window and the previous-step fields of a plane
+  // (loaded one plane ahead)
+  T f0n;
+  T hon[WH ? 9 : 1];
+  float qn[5];
+  auto load_centres = [&](int zq) {
+    const unsigned c = cxy + static_cast<unsigned>(zq) * cst;
+    const unsigned oq = inside ? sxy + static_cast<unsigned>(zq) * plane_bytes : 0u;
+    static_for<0, 5>([&](auto k) { qn[k] = pld<k, kNT>(Qh, oq, qb); });
+    f0n = pld<0>(Fi, c, sb);
+    if constexpr (WH) {
+      static_for<0, Q>([&](auto I) {
+        constexpr int i = I;
+        if constexpr (ho_index(i) >= 0) hon[ho_index(i)] = pld<i>(Hi, c, sb);
+      });
+    }
+  };
+  // first planes of the run
+  {
+    load_centres(zb);
+    static_for<0, Q>([&](auto I) {
+      constexpr int i = I;
+      if constexpr (zf_index(i) >= 0) {
+        constexpr int lo = vcomp(i, 2) > 0 ? -2 : -1;  // window planes lo .. lo + 2
+        static_for<0, 3>([&](auto k) {
+          const unsigned o = zcol(cxy, cst, zplane(P, zb + lo + k, esz));
+          wf[zf_index(i)][k] = pld<i>(Fi, o, sb);
+          if constexpr (WH) wh[zf_index(i)][k] = pld<i>(Hi, o, sb);
+        });
+      } else if constexpr (zl_index(i) >= 0) {
+        static_for<0, 2>([&](auto k) {
+          wl[zl_index(i)][k] = pld<i>(Fi, zcol(cxy, cst, zplane(P, zb - 1 + k, esz)), sb);
+        });
+      }
+    });
+  }
+
+  const int hrow = wv < 2 ? wv : kTY + wv;  // LDS row of this wavefront's halo row
+  for (int z = zb; z < ze; ++z) {
+    const unsigned pz = static_cast<unsigned>(z) * plane_bytes;
+    const unsigned cl = cxy + static_cast<unsigned>(z) * cst;  // this lane's value at z
+    const unsigned cbs = sxy + pz;                             // its storage cell
+    f0c = f0n;
+    if constexpr (WH) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) ho[k] = hon[k];
+    }
+    const double pe = qn[0], gxp = qn[1], gyp = qn[2], gzp = qn[3], pn = qn[4];
+    // obstacle cells: held at the equilibrium of their prescribed fields
+    const bool solid = obst != nullptr && inside && obst[cl / esz] != 0;
+    const bool real = inside && !solid;
+
+    // the planes entering the windows (needed from the streaming phase on):
+    // in flight during the recovery and the streaming phase (the stage
+    // barriers order LDS only)
+    {
+      const unsigned o1 = zcol(cxy, cst, zplane(P, z + 1, esz));
+      const unsigned o2 = zcol(cxy, cst, zplane(P, z + 2, esz));
+      static_for<0, Q>([&](auto I) {
+        constexpr int i = I;
+        if constexpr (zf_index(i) >= 0) {
+          const unsigned o = vcomp(i, 2) > 0 ? o1 : o2;
+          wf[zf_index(i)][3] = pld<i>(Fi, o, sb);
+          if constexpr (WH) wh[zf_index(i)][3] = pld<i>(Hi, o, sb);
+        } else if constexpr (zl_index(i) >= 0) {
+          wl[zl_index(i)][2] = pld<i>(Fi, o1, sb);
+        }
+      });
+    }
+    const double pg2 = 1.0 + (gxp * gxp + gyp * gyp + gzp * gzp);
+    const double ig = 1.0 / sqrt(pg2);
+    const double pux = gxp * ig, puy = gyp * ig, puz = gzp * ig;
+    double E, Mx, My, Mz, N0;
+    moments64<T, WH>(P, fcen, hcen, E, Mx, My, Mz, N0);
+    Fields F;
+    const bool ok = recover<WH>(E, Mx, My, Mz, N0, F);
+    flag_bad(bad_ptr, !ok && real, step_idx);
+    const double omega = P.omega_c / tau_of<T, WH>(P, F, tau_u, nu2e);
+    const double inv1p = 1.0 / (1.0 + omega);
+    const double src = omega * inv1p;
+    T Kt[10];
+    {
+      double K[10], Kp[10];
+      feq_coeffs(P, F.eps, F.ux, F.uy, F.uz, F.g2, K);
+      feq_coeffs(P, pe, pux, puy, puz, pg2, Kp);
+#pragma unroll
+      for (int k = 0; k < 10; ++k) Kt[k] = static_cast<T>(solid ? Kp[k] : src * (2.0 * K[k] - Kp[k]));
+    }
+    T Ht[10];
+    if constexpr (WH) {
+      double H[10], Hp[10];
+      heq_coeffs(P, F.n, F.ux, F.uy, F.uz, F.gam, H);
+      heq_coeffs(P, pn, pux, puy, puz, sqrt(pg2), Hp);
+#pragma unroll
+      for (int k = 0; k < 10; ++k) Ht[k] = static_cast<T>(solid ? Hp[k] : src * (2.0 * H[k] - Hp[k]));
+    }
+    const T tinv = static_cast<T>(solid ? 0.0 : inv1p);
+    const T kinv = static_cast<T>(solid ? 0.0 : kappa_d * inv1p);
+
+    if (real) {
+      pst<0, kNT>(Qh, cbs, qb, static_cast<float>(F.eps));
+      pst<1, kNT>(Qh, cbs, qb, static_cast<float>(F.gam * F.ux));
+      pst<2, kNT>(Qh, cbs, qb, static_cast<float>(F.gam * F.uy));
+      pst<3, kNT>(Qh, cbs, qb, static_cast<float>(F.gam * F.uz));
+      pst<4, kNT>(Qh, cbs, qb, static_cast<float>(F.n));
+    }
+    if (z + 1 < ze) load_centres(z + 1);
+    const unsigned hr = rxy + static_cast<unsigned>(z) * rst;
+    const unsigned hx = xxy + static_cast<unsigned>(z) * xst;
+    const int hcol = lane < 2 ? lane : 64 + lane;
+
+    // limited streaming, bulk term and implicit collision, Eq. (57)
+    T gE = T(0), gX = T(0), gY = T(0), gZ = T(0), gN = T(0), gA = T(0), gAh = T(0);
+    constexpr int NS = (Q + NPS - 1) / NPS;
+    static_for<0, NS>([&](auto st) {
+      constexpr int S0 = st * NPS;
+      constexpr int S1 = S0 + NPS < Q ? S0 + NPS : Q;
+      constexpr int NP = S1 - S0;
+      {
+        // stage the tiles: halo row and halo cells of this plane through
+        // registers, centre row from the windows
+        static_assert(zm_grp(S0) == zm_grp(S1 - 1), "a stage lies in one descriptor group");
+        T vr[NP], vrh[NP], vx[NP], vxh[NP];
+        static_for<0, NP>([&](auto k) {
+          constexpr int i = S0 + k;
+          if constexpr (i != 0) vr[k] = pld<i>(Fi, hr, sb);  // f_0 has no x/y stencil
+          if constexpr (WH && vcomp(i, 1) != 0) vrh[k] = pld<i>(Hi, hr, sb);
+        });
+        if (lane < 4) {
+          static_for<0, NP>([&](auto k) {
+            constexpr int i = S0 + k;
+            if constexpr (i != 0) vx[k] = pld<i>(Fi, hx, sb);
+            if constexpr (WH && vcomp(i, 0) != 0) vxh[k] = pld<i>(Hi, hx, sb);
+          });
+        }
+        // the previous stage's (or plane's) reads of the tiles are done
+        if (st > 0 || z > zb) lds_barrier();
+        static_for<0, NP>([&](auto k) {
+          constexpr int i = S0 + k;
+          if constexpr (i != 0) {
+            lds[k][2 + wv][2 + lane] = fcen(std::integral_constant<int, i>{});
+            lds[k][hrow][2 + lane] = vr[k];
+          }
+          if constexpr (WH && (vcomp(i, 0) != 0 || vcomp(i, 1) != 0))
+            lds[NP + k][2 + wv][2 + lane] = hcen(std::integral_constant<int, i>{});
+          if constexpr (WH && vcomp(i, 1) != 0) lds[NP + k][hrow][2 + lane] = vrh[k];
+        });
+        if (lane < 4) {
+          static_for<0, NP>([&](auto k) {
+            constexpr int i = S0 + k;
+            if constexpr (i != 0) lds[k][2 + wv][hcol] = vx[k];
+            if constexpr (WH && vcomp(i, 0) != 0) lds[NP + k][2 + wv][hcol] = vxh[k];
+          });
+        }
+        lds_barrier();
+      }
+      static_for<S0, S1>([&](auto I) {
+        constexpr int i = I;
+        constexpr Vel e = vel(i);
+        Sten<T> sf, sh;
+        if constexpr (i != 0) gather_xy_lds<T, i, true>(lds[i - S0], sf);
+        if constexpr (zf_index(i) >= 0) {
+          zsten_flux<T, i>(wf[zf_index(i)], sf);
+        } else if constexpr (zl_index(i) >= 0) {
+          sf.v[2][0] = wl[zl_index(i)][0];
+          sf.v[2][1] = wl[zl_index(i)][2];
+        }
+        const T fci = fcen(I);
+        T dD, ns;
+        stream_terms<T, ACT, i, (i != 0)>(sf, fci, dtv, dD, ns);
+        T v = (fci - dD) * tinv + static_cast<T>(weight(i)) * bracket<i>(Kt);
+        if constexpr (i != 0) v += kinv * (ns - NA2 * fci);
+        pst<i, kNT>(Fo, cbs, sb, v);
+        gE += v;
+        gA += fabs(v);
+        if constexpr (e.x != 0) gX += T(e.x) * v;
+        if constexpr (e.y != 0) gY += T(e.y) * v;
+        if constexpr (e.z != 0) gZ += T(e.z) * v;
+        if constexpr (WH) {
+          gather_xy_lds<T, i, false>(lds[NP + (i - S0)], sh);
+          if constexpr (zf_index(i) >= 0) zsten_flux<T, i>(wh[zf_index(i)], sh);
+          const T hci = hcen(I);
+          T dH, nh;
+          stream_terms<T, ACT, i, false>(sh, hci, dtv, dH, nh);
+          const T wpi = i == 0 ? wp[0] : (i <= 6 ? wp[1] : wp[2]);
+          const T hv = (hci - dH) * tinv + wpi * bracket<i>(Ht);
+          pst<i, kNT>(Ho, cbs, sb, hv);
+          gN += hv;
+          gAh += fabs(hv);
+        }
+      });
+    });
+
+    // guard: gate in storage precision with a rounding margin, decide and
+    // blend in FP64 from the stored values (as in k_step)
+    if (P.guard) {
+      constexpr T tol = T(8e-6);
+      const T r2 = static_cast<T>(P.r * P.r), rca = static_cast<T>(P.rca);
+      const T Eg = r2 * gE, mrg = tol * r2 * gA;
+      const T Mg = rca * sqrt(gX * gX + gY * gY + gZ * gZ);
+      bool need = real && (!(Eg > mrg) || (Mg + mrg > static_cast<T>(P.m1) * (Eg - mrg)));
+      if constexpr (WH) {
+        const T Ng = static_cast<T>(P.r) * gN;
+        need = need || (real && !(Ng > static_cast<T>(2.0 * P.efloor * P.gmax) +
+                                           tol * static_cast<T>(P.r) * gAh));
+      }
+      bool fired = false;
+      if (need) {
+        // the stores of this lane are visible to its own loads
+        double E2, Mx2, My2, Mz2, N02;
+        moments64<T, WH>(P, [&](auto I) { return pld<I>(Fo, cbs, sb); },
+                         [&](auto I) { return pld<I>(Ho, cbs, sb); }, E2, Mx2, My2, Mz2, N02);
+        double thf, thh;
+        Fields G;
+        fired = guard_eval<WH>(P, E2, Mx2, My2, Mz2, N02, thf, thh, G);
+        if (fired) {
+          double Kg[10];
+          feq_coeffs(P, G.eps, G.ux, G.uy, G.uz, G.g2, Kg);
+          static_for<0, Q>([&](auto I) {
+            const double ge = weight(I) * bracket<I>(Kg);
+            const double v = static_cast<double>(pld<I>(Fo, cbs, sb));
+            pst<I>(Fo, cbs, sb, static_cast<T>(ge + thf * (v - ge)));
+          });
+          if constexpr (WH) {
+            double Hg[10];
+            heq_coeffs(P, G.n, G.ux, G.uy, G.uz, G.gam, Hg);
+            static_for<0, Q>([&](auto I) {
+              const double ge = wprime<I>(P) * bracket<I>(Hg);
+              const double v = static_cast<double>(pld<I>(Ho, cbs, sb));
+              pst<I>(Ho, cbs, sb, static_cast<T>(ge + thh * (v - ge)));
+            });
+          }
+        }
+      }
+      count_events(guard_ptr, fired);
+    }
+
+    // next plane: shift the windows
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+      wf[k][0] = wf[k][1];
+      wf[k][1] = wf[k][2];
+      wf[k][2] = wf[k][3];
+      if constexpr (WH) {
+        wh[k][0] = wh[k][1];
+        wh[k][1] = wh[k][2];
+        wh[k][2] = wh[k][3];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      wl[k][0] = wl[k][1];
+      wl[k][1] = wl[k][2];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Temporal blocking of 1D domains: one launch advances KB <= kTbMax steps.
 // A workgroup holds a region of kBlock consecutive cells (one per thread):
 // its populations and previous fields stay in registers across the steps and
@@ -1672,6 +2164,15 @@ __global__ __launch_bounds__(kBlock) void k_sums_final(const double* partial, in
 
 template <typename T, int ACT, bool WH, bool EU>
 hipError_t launch_step_t(const StepParams& p, hipStream_t s) {
+  if constexpr (ACT == 7 && !EU && std::is_same<T, float>::value) {
+    if (p.zm_len > 0) {
+      const long long nblk = p.zm_per_xcd * kXcds;
+      hipLaunchKernelGGL((k_step_zm<T, WH>), dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, s,
+                         static_cast<const T*>(p.f_in), static_cast<T*>(p.f_out),
+                         static_cast<const T*>(p.h_in), static_cast<T*>(p.h_out), p.hist, p.obst, p);
+      return hipGetLastError();
+    }
+  }
   const long long nblk = p.tiles_per_xcd * kXcds;
   hipLaunchKernelGGL((k_step<T, ACT, WH, EU, false>), dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0,
                      s, static_cast<const T*>(p.f_in), static_cast<T*>(p.f_out),
