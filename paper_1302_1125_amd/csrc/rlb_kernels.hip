@@ -1274,6 +1274,11 @@ constexpr int kNT = RLB_STREAMING ? 2 : 0;
 #ifndef RLB_ZM_STAGES
 #define RLB_ZM_STAGES 2
 #endif
+// wave priority while a z-marching wave issues a burst of loads (0: off);
+// measured on MI355X: 0.6% faster at 384^3
+#ifndef RLB_ZM_PRIO
+#define RLB_ZM_PRIO 1
+#endif
 // populations staged through LDS together (f and h) in the z-marching step
 constexpr int kZmPops = (Q + RLB_ZM_STAGES - 1) / RLB_ZM_STAGES;
 
@@ -1413,6 +1418,7 @@ __global__ __launch_bounds__(kBlock, RLB_ZM_OCC) void k_step_zm(
     // the planes entering the windows (needed from the streaming phase on):
     // in flight during the recovery and the streaming phase (the stage
     // barriers order LDS only)
+    if (RLB_ZM_PRIO) __builtin_amdgcn_s_setprio(RLB_ZM_PRIO);
     {
       const unsigned o1 = zcol(cxy, cst, zplane(P, z + 1, esz));
       const unsigned o2 = zcol(cxy, cst, zplane(P, z + 2, esz));
@@ -1427,6 +1433,7 @@ __global__ __launch_bounds__(kBlock, RLB_ZM_OCC) void k_step_zm(
         }
       });
     }
+    if (RLB_ZM_PRIO) __builtin_amdgcn_s_setprio(0);
     const double pg2 = 1.0 + (gxp * gxp + gyp * gyp + gzp * gzp);
     const double ig = 1.0 / sqrt(pg2);
     const double pux = gxp * ig, puy = gyp * ig, puz = gzp * ig;
@@ -1480,6 +1487,7 @@ __global__ __launch_bounds__(kBlock, RLB_ZM_OCC) void k_step_zm(
         // stage the tiles: halo row and halo cells of this plane through
         // registers, centre row from the windows
         static_assert(zm_grp(S0) == zm_grp(S1 - 1), "a stage lies in one descriptor group");
+        if (RLB_ZM_PRIO) __builtin_amdgcn_s_setprio(RLB_ZM_PRIO);
         T vr[NP], vrh[NP], vx[NP], vxh[NP];
         static_for<0, NP>([&](auto k) {
           constexpr int i = S0 + k;
@@ -1493,6 +1501,7 @@ __global__ __launch_bounds__(kBlock, RLB_ZM_OCC) void k_step_zm(
             if constexpr (WH && vcomp(i, 0) != 0) vxh[k] = pld<i>(Hi, hx, sb);
           });
         }
+        if (RLB_ZM_PRIO) __builtin_amdgcn_s_setprio(0);
         // the previous stage's (or plane's) reads of the tiles are done
         if (st > 0 || z > zb) lds_barrier();
         static_for<0, NP>([&](auto k) {
