@@ -247,7 +247,8 @@ def serving(args):
     nu, dt = args.serving_nu, 0.25
     if args.serving_stabilised:
         nu, dt = W.STABILISED["nu"], W.STABILISED["dt"]
-    common = rlb.config_from(8, precision=rlb.RLB_MIXED, tau_mode=rlb.RLB_TAU_ETA_OVER_S,
+    serve_prec = rlb.RLB_FP64 if args.serving_precision == "fp64" else rlb.RLB_MIXED
+    common = rlb.config_from(8, precision=serve_prec, tau_mode=rlb.RLB_TAU_ETA_OVER_S,
                              with_density=True, dt_over_dx=dt, guard_umax=0.9999, nu=nu)
 
     def prepare(qs):
@@ -278,6 +279,15 @@ def serving(args):
             srv.rlb_server_result(i, raise_inadmissible=False)
         cst = srv.rlb_server_stats_get()
     cap_lups = cst.cell_updates / cst.busy_seconds
+    # the same batch served in FP64: batching at identical precision
+    common64 = rlb.config_from(8, precision=rlb.RLB_FP64, tau_mode=rlb.RLB_TAU_ETA_OVER_S,
+                               with_density=True, dt_over_dx=dt, guard_umax=0.9999, nu=nu)
+    with rlb.Server(common64, budget, args.chunk) as srv:
+        ids = [srv.submit_request(q) for q in calib]
+        for i in ids:
+            srv.rlb_server_result(i, raise_inadmissible=False)
+        cst64 = srv.rlb_server_stats_get()
+    cap64_lups = cst64.cell_updates / cst64.busy_seconds
     rate = args.load * cap_lups / (sum(lups) / len(lups))
     rng = np.random.default_rng(W.SEED_BASE + 4)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, len(reqs)))
@@ -286,6 +296,12 @@ def serving(args):
         f"{sum(lups) / 1e9:.1f} G cell-updates requested")
 
     ids = [None] * len(reqs)
+    # requests of the one-at-a-time sample (stratified by size): their served
+    # fields are kept for the accuracy comparison
+    order = np.argsort([q.n for q in reqs])
+    pick = order[np.linspace(0, len(order) - 1, args.baseline_sample).astype(int)]
+    pick_set = set(int(k) for k in pick)
+    served = {}
     with rlb.Server(common, budget, args.chunk) as srv:
         start = time.perf_counter()
 
@@ -305,6 +321,8 @@ def serving(args):
             while ids[k] is None:
                 time.sleep(0.001)
             out, l, bad, gev, st = srv.rlb_server_result(ids[k], raise_inadmissible=False)
+            if k in pick_set:
+                served[k] = (out, bad)
             lat.append(l)
             failed += int(bad >= 0)
             guard += gev
@@ -318,22 +336,36 @@ def serving(args):
     # sample stratified by size give the rate as a function of n; the time
     # the whole stream would take one at a time is the sum over requests of
     # n * steps / rate(n), interpolated in log n
-    order = np.argsort([q.n for q in reqs])
-    pick = order[np.linspace(0, len(order) - 1, args.baseline_sample).astype(int)]
-    sample_n, sample_rate = [], []
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+    sample_n, sample_rate, acc = [], [], []
+    fp64_failed = 0
     for k in pick:
         q = reqs[k]
         w = q.workload(precision=rlb.RLB_FP64, nu=nu, dt=dt)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx = rlb.context_for_workload(w, precision=rlb.RLB_FP64)
-        ctx.status_of_step(q.steps)
-        ctx.rlb_moments()
+        st_ = ctx.status_of_step(q.steps)
+        f64 = ctx.rlb_moments()
         ctx.close()
         r = q.n * q.steps / (time.perf_counter() - t0)
         sample_n.append(q.n)
         sample_rate.append(r)
-        log(f"one-at-a-time FP64 n={q.n} steps={q.steps}: {r / 1e6:.0f} MLUPS")
+        fp64_failed += int(st_ != 0)
+        out, bad = served[int(k)]
+        if st_ == 0 and bad < 0:
+            # the served (batched) result against the same request solved
+            # alone in FP64: rel. L2 per field (0 when serving in FP64: the
+            # batched step is the context path's arithmetic)
+            e64, ux64, n64 = (np.ravel(f64[j]) for j in (0, 1, 4))
+            g64 = 1.0 / np.sqrt(1.0 - ux64 ** 2)
+            gm = 1.0 / np.sqrt(1.0 - out[1] ** 2)
+            acc.append((rel(out[0], e64), rel(out[4], n64), rel(gm * out[1], g64 * ux64),
+                        all(np.array_equal(np.ravel(out[j]), np.ravel(f64[j])) for j in range(5))))
+        log(f"one-at-a-time FP64 n={q.n} steps={q.steps}: {r / 1e6:.0f} MLUPS"
+            + ("" if st_ == 0 else " (inadmissible)"))
     rate_of = lambda n: float(np.interp(np.log(n), np.log(sample_n), sample_rate))
     base_s = sum(q.n * q.steps / rate_of(q.n) for q in reqs)
     base = sum(lups) / base_s / 1e6
@@ -342,8 +374,10 @@ def serving(args):
     out = {
         "metric": "p50/p99 latency of batched solves & aggregate MLUPS",
         "value": round(agg, 2), "unit": "MLUPS", "n_gpus": 1, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32-storage/f64-recovery", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if serve_prec == rlb.RLB_FP64 else "f32-storage/f64-recovery", "data": "synthetic",
         "config": {"workload": "serving_shock_tubes_1d", "mix": args.serving_mix, "requests": len(reqs),
+                   "precision": args.serving_precision,
                    "nu": nu, "dt_over_dx": dt, "stabilised": bool(args.serving_stabilised),
                    "offered_load": args.load, "rate_per_s": round(rate, 3), "chunk_steps": args.chunk,
                    "arena_cells": int(sst.capacity_cells),
@@ -362,6 +396,15 @@ def serving(args):
                                "est_seconds": round(base_s, 2)},
         "speedup_vs_one_at_a_time_fp64": round(agg / base, 2),
         "capacity_speedup_vs_one_at_a_time_fp64": round(cap_lups / 1e6 / base, 2),
+        "capacity_fp64_batched_mlups": round(cap64_lups / 1e6, 1),
+        "capacity_speedup_fp64_batched_vs_one_at_a_time_fp64": round(cap64_lups / 1e6 / base, 2),
+        "one_at_a_time_fp64_failed_in_sample": fp64_failed,
+        "accuracy_served_vs_fp64_alone": (
+            {"requests": len(acc), "bitwise_equal": int(sum(a[3] for a in acc)),
+             "eps": {"median": float(np.median([a[0] for a in acc])), "max": float(max(a[0] for a in acc))},
+             "n": {"median": float(np.median([a[1] for a in acc])), "max": float(max(a[1] for a in acc))},
+             "gamma_u": {"median": float(np.median([a[2] for a in acc])), "max": float(max(a[2] for a in acc))}}
+            if acc else None),
     }
     print(json.dumps(out), flush=True)
 
@@ -391,13 +434,16 @@ def main():
     ap.add_argument("--serving-budget-gib", type=float, default=16.0)
     ap.add_argument("--serving-nu", type=float, default=4.0)
     ap.add_argument("--serving-mix", default="stated", choices=["stated", "paper"])
+    ap.add_argument("--serving-precision", default="fp64", choices=["mixed", "fp64"],
+                    help="precision of the batched server (fp64: the same arithmetic as the "
+                         "one-at-a-time FP64 baseline, results bitwise equal to it)")
     ap.add_argument("--stabilised", action="store_true",
                     help="run the grid workload under the stabilised parameter set (nu = 4, alpha = 0.1, "
                          "dt = 0.075)")
     ap.add_argument("--serving-stabilised", action="store_true",
                     help="serve under the stabilised parameter set (nu = 4, alpha = 0.1, dt = 0.075) "
                          "over the same physical run times")
-    ap.add_argument("--baseline-sample", type=int, default=12)
+    ap.add_argument("--baseline-sample", type=int, default=48)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
