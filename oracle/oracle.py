@@ -20,6 +20,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 Q = 19
 BC_PERIODIC, BC_FIXED, BC_OUTFLOW = 0, 1, 2
 TAU_UNIFORM, TAU_ETA_OVER_S = 0, 1
+DENSW_PAPER, DENSW_ISOTROPIC = 0, 1
 
 _lib = None
 
@@ -44,7 +45,7 @@ class _Cfg(ctypes.Structure):
         ("alpha", ctypes.c_double), ("with_h", ctypes.c_int),
         ("bc", ctypes.c_int * 6), ("face", (ctypes.c_double * 5) * 6),
         ("guard_umax", ctypes.c_double), ("guard_efloor", ctypes.c_double),
-        ("basic", ctypes.c_int),
+        ("basic", ctypes.c_int), ("dens_w", ctypes.c_int),
     ]
 
 
@@ -56,9 +57,10 @@ def _load():
         build(force=True)
     L = ctypes.CDLL(_LIB_PATH)
     dp = ctypes.POINTER(ctypes.c_double)
-    L.orc_lattice.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp, dp, dp]
+    L.orc_lattice.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                              dp, dp, dp]
     L.orc_feq.argtypes = [ctypes.c_double, ctypes.c_int] + [ctypes.c_double] * 4 + [dp]
-    L.orc_heq.argtypes = [ctypes.c_double, ctypes.c_int] + [ctypes.c_double] * 4 + [dp]
+    L.orc_heq.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int] + [ctypes.c_double] * 4 + [dp]
     L.orc_moments.argtypes = [ctypes.c_double, ctypes.c_int, dp, dp, dp, dp]
     L.orc_recover.argtypes = [ctypes.c_double] * 5 + [ctypes.c_int, dp]
     L.orc_recover.restype = ctypes.c_int
@@ -92,15 +94,17 @@ def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
 
-def lattice(nu: float, basic: bool = False):
+def lattice(nu: float, basic: bool = False, density_weights: int = 0):
     """(e[19,3] int, xi[19,4], w[19], w'[19]) in the oracle's own order; the
-    extended set (Sec. II.A) or, with basic=True, the basic set (Sec. II)."""
+    extended set (Sec. II.A) or, with basic=True, the basic set (Sec. II);
+    density_weights: DENSW_PAPER (Eqs. (59)-(60)) or DENSW_ISOTROPIC."""
     L = _load()
     e = np.zeros((Q, 3), dtype=np.int32)
     xi = np.zeros((Q, 4))
     w = np.zeros(Q)
     wp = np.zeros(Q)
-    L.orc_lattice(nu, int(basic), e.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _p(xi), _p(w), _p(wp))
+    L.orc_lattice(nu, int(basic), int(density_weights), e.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                  _p(xi), _p(w), _p(wp))
     return e.astype(np.int64), xi, w, wp
 
 
@@ -110,9 +114,9 @@ def feq(nu, eps, ux, uy, uz, basic: bool = False) -> np.ndarray:
     return out
 
 
-def heq(nu, n, ux, uy, uz, basic: bool = False) -> np.ndarray:
+def heq(nu, n, ux, uy, uz, basic: bool = False, density_weights: int = 0) -> np.ndarray:
     out = np.zeros(Q)
-    _load().orc_heq(nu, int(basic), n, ux, uy, uz, _p(out))
+    _load().orc_heq(nu, int(basic), int(density_weights), n, ux, uy, uz, _p(out))
     return out
 
 
@@ -150,6 +154,7 @@ class Config:
     guard_umax: float = 0.0
     guard_efloor: float = 1e-10
     basic: bool = False  # the basic model of Sec. II (dt, euler, alpha, guard unused/off)
+    density_weights: int = 0  # DENSW_PAPER | DENSW_ISOTROPIC (extended set)
 
     def _c(self) -> _Cfg:
         c = _Cfg()
@@ -165,6 +170,7 @@ class Config:
                 c.face[k][j] = float(self.face[k][j])
         c.guard_umax, c.guard_efloor = self.guard_umax, self.guard_efloor
         c.basic = int(self.basic)
+        c.dens_w = int(self.density_weights)
         return c
 
 

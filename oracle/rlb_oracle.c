@@ -68,8 +68,17 @@ typedef struct {
    rest, c_a(+-1,0,0)_FS, c_a(+-1,+-1,0)_FS with c_a = sqrt(19)/nu and the
    same c_t/c_0 and c_0; weights w_0 = 1 + 4 c_t^2 nu^2/(361 c_0^2)
    - c_t^2/(c_a^2 c_0^2), w_1..6 = c_t^2 (361 - 8 c_a^2 nu^2)/(2166 c_0^2 c_a^2),
-   w_7..18 = c_t^2 nu^2/(1083 c_0^2); no density weights (f only). */
-static void make_lattice(double nu, int basic, lattice_t* L) {
+   w_7..18 = c_t^2 nu^2/(1083 c_0^2); no density weights (f only).
+   Density weights (extended set).  Eq. (58) needs sum_i w'_i = 1 and
+   sum_i w'_i c^a c^b = delta^{ab}/3 (so that N^mu = n U^mu); with one weight
+   per shell that leaves one free parameter.  dens_w = ORC_DENSW_PAPER takes
+   the paper's choice, Eqs. (59)-(60) (w'_0 = 1/10; the diagonal weight is
+   negative for c_a^2 > 10/9, e.g. at nu = 27^(1/4)).  dens_w =
+   ORC_DENSW_ISOTROPIC (not in the paper) fixes the free parameter by
+   isotropy of the fourth moment instead, sum w' (c^x)^4 = 3 sum w' (c^x)^2
+   (c^y)^2: w'_7..18 = 1/(288 c_a^2), w'_1..6 = 1/(9 c_a^2), w'_0 = 1 -
+   17/(24 c_a^2), all non-negative for c_a^2 >= 17/24 (nu <= 4.28). */
+static void make_lattice(double nu, int basic, int dens_w, lattice_t* L) {
   memset(L, 0, sizeof(*L));
   L->nu = nu;
   L->basic = basic;
@@ -102,9 +111,15 @@ static void make_lattice(double nu, int basic, lattice_t* L) {
     w0 = 1.0 + 7.0 * r2 * nu2 / 676.0 - r2 / ca2;
     w1 = r2 / (1014.0 * ca2) * (169.0 - 2.0 * ca2 * nu2);
     w2 = r2 * nu2 / 8112.0;
-    wp0 = 1.0 / 10.0;
-    wp1 = 6.0 / 35.0 - 1.0 / (42.0 * ca2);
-    wp2 = 1.0 / (84.0 * ca2) - 3.0 / 280.0;
+    if (dens_w == ORC_DENSW_ISOTROPIC) {
+      wp0 = 1.0 - 17.0 / (24.0 * ca2);
+      wp1 = 1.0 / (9.0 * ca2);
+      wp2 = 1.0 / (288.0 * ca2);
+    } else {
+      wp0 = 1.0 / 10.0;
+      wp1 = 6.0 / 35.0 - 1.0 / (42.0 * ca2);
+      wp2 = 1.0 / (84.0 * ca2) - 3.0 / 280.0;
+    }
   }
   for (int i = 0; i < ORC_Q; ++i) {
     const int zeros = (L->e[i][0] == 0) + (L->e[i][1] == 0) + (L->e[i][2] == 0);
@@ -116,9 +131,9 @@ static void make_lattice(double nu, int basic, lattice_t* L) {
   }
 }
 
-void orc_lattice(double nu, int basic, int* e, double* xi, double* w, double* wp) {
+void orc_lattice(double nu, int basic, int dens_w, int* e, double* xi, double* w, double* wp) {
   lattice_t L;
-  make_lattice(nu, basic, &L);
+  make_lattice(nu, basic, dens_w, &L);
   for (int i = 0; i < ORC_Q; ++i) {
     for (int a = 0; a < 3; ++a) e[3 * i + a] = L.e[i][a];
     for (int a = 0; a < 4; ++a) xi[4 * i + a] = L.xi[i][a];
@@ -183,14 +198,14 @@ static void heq_L(const lattice_t* L, double n, double ux, double uy,
 void orc_feq(double nu, int basic, double eps, double ux, double uy, double uz,
              double* feq) {
   lattice_t L;
-  make_lattice(nu, basic, &L);
+  make_lattice(nu, basic, ORC_DENSW_PAPER, &L);
   feq_L(&L, eps, ux, uy, uz, feq);
 }
 
-void orc_heq(double nu, int basic, double n, double ux, double uy, double uz,
+void orc_heq(double nu, int basic, int dens_w, double n, double ux, double uy, double uz,
              double* heq) {
   lattice_t L;
-  make_lattice(nu, basic, &L);
+  make_lattice(nu, basic, dens_w, &L);
   heq_L(&L, n, ux, uy, uz, heq);
 }
 
@@ -211,7 +226,7 @@ static void moments_L(const lattice_t* L, const double* f, long fs,
 void orc_moments(double nu, int basic, const double* f, const double* h, double* T0,
                  double* N0) {
   lattice_t L;
-  make_lattice(nu, basic, &L);
+  make_lattice(nu, basic, ORC_DENSW_PAPER, &L); /* the moments do not use w' */
   moments_L(&L, f, 1, h, 1, T0, N0);
 }
 
@@ -307,9 +322,13 @@ orc_state* orc_create(const orc_config* cfg) {
   }
   if (cfg->basic && (cfg->euler || cfg->alpha != 0.0 || cfg->guard_umax > 0 || cfg->with_h))
     return NULL;
+  if (cfg->dens_w != ORC_DENSW_PAPER && cfg->dens_w != ORC_DENSW_ISOTROPIC) return NULL;
+  if (cfg->dens_w == ORC_DENSW_ISOTROPIC &&
+      (cfg->basic || 13.0 / (cfg->nu * cfg->nu) < 17.0 / 24.0))
+    return NULL; /* extended set only; w'_0 >= 0 needs c_a^2 >= 17/24 */
   orc_state* S = (orc_state*)calloc(1, sizeof(orc_state));
   S->cfg = *cfg;
-  make_lattice(cfg->nu, cfg->basic, &S->L);
+  make_lattice(cfg->nu, cfg->basic, cfg->dens_w, &S->L);
   S->ncell = 1;
   S->npad = 1;
   for (int a = 0; a < 3; ++a) {

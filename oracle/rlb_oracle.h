@@ -43,19 +43,25 @@ typedef struct {
                          streaming with dt = c_t dx/(c_a c_0), explicit Marle
                          collision, no bulk term, no limiter, f only); euler,
                          alpha, with_h and the guard must be off; dt unused   */
+  int dens_w;         /* density weights w'_i of Eq. (58): ORC_DENSW_PAPER
+                         (Eqs. (59)-(60)) or ORC_DENSW_ISOTROPIC (beyond the
+                         paper, see make_lattice); extended set only          */
 } orc_config;
+
+enum { ORC_DENSW_PAPER = 0, ORC_DENSW_ISOTROPIC = 1 };
 
 typedef struct orc_state orc_state;
 
 /* Lattice (basic = 0: the extended set of Sec. II.A, Eq. (42); basic = 1: the
    basic D3Q19 set of Sec. II): velocity e_i (integer, 3 per pop), 4-vector
    xi_i = (c_t/c_0, c_a e_i), weights w_i and density weights w'_i. */
-void orc_lattice(double nu, int basic, int* e /*19x3*/, double* xi /*19x4*/,
+void orc_lattice(double nu, int basic, int dens_w, int* e /*19x3*/, double* xi /*19x4*/,
                  double* w /*19*/, double* wp /*19*/);
 
 /* Discrete equilibria (reading M of Eq. (29) fixed by Eq. (36)) and Eq. (58). */
 void orc_feq(double nu, int basic, double eps, double ux, double uy, double uz, double* feq);
-void orc_heq(double nu, int basic, double n, double ux, double uy, double uz, double* heq);
+void orc_heq(double nu, int basic, int dens_w, double n, double ux, double uy, double uz,
+             double* heq);
 
 /* Moments T^{00}, T^{0a} of f and N^0 of h; fields (eps,ux,uy,uz,n) from them.
    Returns 0 if admissible, -1 if not (fields then hold NaN). */

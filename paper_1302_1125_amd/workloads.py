@@ -27,6 +27,7 @@ FP64, MIXED = 0, 1
 COLL_IMPLICIT, COLL_EULER = 0, 1
 TAU_UNIFORM, TAU_ETA_OVER_S = 0, 1
 LATTICE_EXTENDED, LATTICE_BASIC = 0, 1
+DENSW_PAPER, DENSW_ISOTROPIC = 0, 1  # density weights of Eq. (58): Eqs. (59)-(60) | isotropic
 
 
 @dataclass
@@ -50,6 +51,7 @@ class Workload:
     guard_umax: float = 0.0
     guard_efloor: float = 1e-10
     lattice: int = LATTICE_EXTENDED
+    density_weights: int = DENSW_PAPER
     eps: Optional[np.ndarray] = None
     ux: Optional[np.ndarray] = None
     uy: Optional[np.ndarray] = None
