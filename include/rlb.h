@@ -61,6 +61,7 @@ enum { RLB_COLL_IMPLICIT = 0, RLB_COLL_EULER = 1 }; /* Eq. (57) | Sec. III     *
 enum { RLB_TAU_UNIFORM = 0, RLB_TAU_ETA_OVER_S = 1 };
 enum { RLB_BC_PERIODIC = 0, RLB_BC_FIXED = 1, RLB_BC_OUTFLOW = 2 };
 enum { RLB_LATTICE_EXTENDED = 0, RLB_LATTICE_BASIC = 1 };  /* Sec. II.A | Sec. II */
+enum { RLB_DENSW_PAPER = 0, RLB_DENSW_ISOTROPIC = 1 };      /* density weights */
 
 /* Run configuration.  Lattice units: delta x = 1. */
 typedef struct {
@@ -120,6 +121,22 @@ typedef struct {
                            density distribution for the extended set only),
                            alpha = 0 and guard_umax = 0.  The explicit
                            collision is stable only for omega < 2.          */
+  int32_t density_weights; /* weights w'_i of the density equilibrium,
+                           Eq. (58), which fixes them only through
+                           sum w' = 1 and sum w' c^a c^b = delta^{ab}/3 (one
+                           free parameter with one weight per shell).
+                           RLB_DENSW_PAPER (default): Eqs. (59)-(60),
+                           w'_0 = 1/10; the diagonal weight is negative for
+                           c_a^2 = 13/nu^2 > 10/9 (nu < 3.42), where the
+                           density part is linearly unstable for uniform
+                           flows faster than |u| ~ 0.2.
+                           RLB_DENSW_ISOTROPIC (not in the paper): the free
+                           parameter fixed by isotropy of the fourth moment,
+                           w' = (1 - 17/(24 c_a^2), 1/(9 c_a^2),
+                           1/(288 c_a^2)), non-negative; no linear growth of
+                           the density part up to |u| = 0.995 at dt 0.25
+                           (1D) and 0.15 (3D).  Extended lattice only, and
+                           nu <= sqrt(13 * 24/17) = 4.28.                   */
 } rlb_config;
 
 typedef struct {

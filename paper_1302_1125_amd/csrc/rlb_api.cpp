@@ -93,6 +93,11 @@ rlb_status validate(const rlb_config* c) {
   } else if (!(c->dt_over_dx > 0 && c->dt_over_dx <= 0.5)) {
     return fail(RLB_E_INVALID_ARG, "dt_over_dx in (0, 0.5]");
   }
+  if (c->density_weights != RLB_DENSW_PAPER && c->density_weights != RLB_DENSW_ISOTROPIC)
+    return fail(RLB_E_INVALID_ARG, "density_weights");
+  if (c->density_weights == RLB_DENSW_ISOTROPIC &&
+      (c->lattice != RLB_LATTICE_EXTENDED || 13.0 / (c->nu * c->nu) < 17.0 / 24.0))
+    return fail(RLB_E_INVALID_ARG, "isotropic density weights: extended lattice, nu <= 4.28");
   if (c->tau_mode == RLB_TAU_UNIFORM && !(c->tau > 0 && std::isfinite(c->tau)))
     return fail(RLB_E_INVALID_ARG, "tau must be > 0");
   if (!(c->eta_over_s >= 0 && std::isfinite(c->eta_over_s))) return fail(RLB_E_INVALID_ARG, "eta_over_s >= 0");
@@ -268,9 +273,16 @@ void fill_constants(const rlb_config& c, rlb::StepParams& p) {
   p.ca2 = ca2nu2 / (nu * nu);
   p.rca = p.r * p.ca;
   p.inv_r = nu / std::sqrt(27.0);
-  p.wp0 = 0.1;
-  p.wp1 = 6.0 / 35.0 - 1.0 / (42.0 * p.ca2);
-  p.wp2 = 1.0 / (84.0 * p.ca2) - 3.0 / 280.0;
+  if (c.density_weights == RLB_DENSW_ISOTROPIC) {
+    // sum w' = 1, sum w' c^a c^b = delta/3 and an isotropic fourth moment
+    p.wp0 = 1.0 - 17.0 / (24.0 * p.ca2);
+    p.wp1 = 1.0 / (9.0 * p.ca2);
+    p.wp2 = 1.0 / (288.0 * p.ca2);
+  } else {  // Eqs. (59)-(60)
+    p.wp0 = 0.1;
+    p.wp1 = 6.0 / 35.0 - 1.0 / (42.0 * p.ca2);
+    p.wp2 = 1.0 / (84.0 * p.ca2) - 3.0 / 280.0;
+  }
   p.k1 = 4.0 * std::sqrt(ca2nu2 / 27.0);
   p.omega_c = nu * nu * dt / std::sqrt(27.0);
   p.kappa = p.omega_c * c.alpha;

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layout_matches_header():
     from paper_1302_1125_amd import rlb
-    # sizeof(rlb_config) in C: 4 + 3*4 + 4*4 + 5*8 + 6*4 + 30*8 + 2*8 + 4, padded to 8
+    # sizeof(rlb_config) in C: 4 + 3*4 + 4*4 + 5*8 + 6*4 + 30*8 + 2*8 + 2*4
     assert ctypes.sizeof(rlb.rlb_config) == 360
     assert ctypes.sizeof(rlb.rlb_stats) == 64
     assert ctypes.sizeof(rlb.rlb_request) == 168

@@ -167,3 +167,19 @@ def test_weak_3d_cloud_viscous(rlb):
     rows = _paired(rlb, w_m, w_d, [200, 600])
     for r in rows:
         _within(r["mixed"], SHORT)
+
+
+def test_weak_3d_cloud_isotropic_density_weights(rlb):
+    """The same inviscid weak 3D cloud over its 1000 steps with the isotropic
+    density weights (RLB_DENSW_ISOTROPIC, non-negative): the density part is
+    now linearly stable at these speeds, one ulp on the FP64 input stays at
+    round-off in every field, and mixed vs FP64 is small in n as well --
+    measured eps 3.9e-5, n 2.0e-5, gamma u 4.8e-5 at step 1000 (with the
+    paper's weights n differs by 0.50); bounds 2.5x that."""
+    w_m = W.shock_cloud_3d(regime="weak", precision=W.MIXED).copy_with(density_weights=W.DENSW_ISOTROPIC)
+    w_d = W.shock_cloud_3d(regime="weak", precision=W.FP64).copy_with(density_weights=W.DENSW_ISOTROPIC)
+    rows = _paired(rlb, w_m, w_d, [200, 600, 1000], perturb=True)
+    for r in rows:
+        _within(r["mixed"], {"eps": 1e-4, "n": 5e-5, "gu": 1.2e-4})
+        assert max(r["fp64_ulp"].values()) < 1e-12
+        assert r["guard"] == [0, 0]
