@@ -444,6 +444,8 @@ def main():
                     help="serve under the stabilised parameter set (nu = 4, alpha = 0.1, dt = 0.075) "
                          "over the same physical run times")
     ap.add_argument("--baseline-sample", type=int, default=48)
+    ap.add_argument("--density-weights", default="paper", choices=["paper", "isotropic"],
+                    help="density weights of Eq. (58): the paper's (default) or the isotropic set")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -486,6 +488,9 @@ def main():
         # were taken under the default set, so none is reported
         from paper_1302_1125_amd import workloads as W
         w = W.stabilised(w).copy_with(name=w.name + "_stabilised")
+    if args.density_weights == "isotropic" and w.with_density:
+        # same traffic and kernel; only the three density weights differ
+        w = w.copy_with(density_weights=rlb.RLB_DENSW_ISOTROPIC)
     # a dedicated stream (default priority): the library launches on it and
     # the timing events are recorded on it
     stream = torch.cuda.Stream()
@@ -553,6 +558,13 @@ def main():
                    "alpha": w.alpha, "guard_events": stats.guard_events,
                    "first_bad_step": stats.first_bad_step,
                    "timed_steps": [args.warmup, args.warmup + args.steps],
+                   "stated_steps": w.steps,
+                   # the guarded long runs grow past a few hundred steps (scheme as
+                   # read): the timed window is then the early transient
+                   "timed_phase": ("early transient" if args.warmup + args.steps < w.steps
+                                   else "whole run"),
+                   "density_weights": ("isotropic" if w.density_weights == rlb.RLB_DENSW_ISOTROPIC
+                                       else "paper") if w.with_density else None,
                    "bytes_per_cell_update": bpc, "stored_bytes_per_cell_update": stored},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
