@@ -446,3 +446,52 @@ def test_stabilised_parameters_keep_the_riemann_plateau(euler):
     hi = int(nx / 2 + t * (s.right_head - 0.15 * (s.right_head - s.left_tail)))
     assert abs(np.median(ux[lo:hi]) / s.vstar - 1.0) < 2e-3
     assert abs(np.median(eps[lo:hi] / 3.0) / s.pstar - 1.0) < 5e-3
+
+
+def test_split_flux_of_left_movers_is_not_upwind(oracle_mod):
+    """Diagnosis of the energy-momentum part's growth (the open half of the
+    admissibility-preserving extension).  In Euler mode one step moves the
+    moments by the flux-vector splitting A+ = K P+ J (populations moving in
+    +x) and A- = K P- J (-x); an upwind splitting needs A- <= 0 <= A+.  At
+    rest it holds; for a flow along +x the left movers' Jacobian A- gets
+    positive eigenvalues (0.10 at u = 0.3, all four positive from u = 0.7):
+    those populations carry some characteristic quantities the wrong way,
+    which the upwind differences then amplify.  The one free direction of
+    the equilibrium that Eq. (36) leaves (c (|xi|^2 - (xi^0)^2) w_i, c a
+    multiple of eps) does not remove it: over c in [-0.4, 0] eps the growth of
+    the gamma = 10 slabs' parameters at u = 0.5 stays at 2.4e-4 per step."""
+    O = oracle_mod
+    p = _speeds(O, NU0)[:, 0]
+    Pp, Pm = np.diag(np.maximum(p, 0.0)), np.diag(np.minimum(p, 0.0))
+
+    def split(u):
+        K, J, _, _ = _f_linear(O, NU0, u)
+        return np.linalg.eigvals(K @ Pp @ J).real, np.linalg.eigvals(K @ Pm @ J).real
+
+    ap, am = split(0.0)
+    assert ap.min() > 0.0 and am.max() < 0.0
+    _, am3 = split(0.3)
+    assert am3.max() > 0.05
+    _, am7 = split(0.7)
+    assert am7.min() > 0.0
+
+    e, xi, w, _ = O.lattice(NU0)
+    nvec = w * ((xi[:, 1:] ** 2).sum(1) - xi[:, 0] ** 2)
+    K0 = np.stack([O.moments(NU0, np.eye(19)[i])[0] for i in range(19)], 1)
+    assert abs(K0 @ nvec).max() < 1e-12  # invisible to T^{0 mu}
+    dt, tau, alpha, u = 0.25, 0.76, 0.0048, 0.5
+
+    def growth(c):
+        U0 = O.moments(NU0, O.feq(NU0, 3.0, u, 0.0, 0.0) + c * 3.0 * nvec)[0]
+
+        def f_of_U(U):
+            rc, fl = O.recover(U, 0.0, with_h=False)
+            return O.feq(NU0, fl[0], fl[1], fl[2], fl[3]) + c * fl[0] * nvec
+
+        h = 1e-5 * U0[0]
+        J = np.stack([_fd(f_of_U, U0, k, h) for k in range(4)], 1)
+        G = lambda t: _f_matrix(O, NU0, u, dt, tau, alpha, t, (K0, J, None, None))
+        return _growth(G, 61)
+
+    rates = [growth(c) for c in (-0.4, -0.2, 0.0)]
+    assert min(rates) > 2e-4, rates
