@@ -179,3 +179,30 @@ def test_segment_ends_equal_context_path_and_oracle(rlb, ends):
         errs = field_errors([a.reshape(w.shape) for a in out[0]], o.fields(), keys=("eps", "p", "n", "gux"))
         assert max(errs.values()) <= 1e-10, errs
     assert compared >= 2
+
+
+def test_served_isotropic_density_weights(rlb):
+    """The server honours the common config's density weights: with the
+    isotropic set at the default nu = 27^(1/4) (where the paper's diagonal
+    density weight is negative), served results equal the context path bit
+    for bit and the FP64 oracle with the same weights to 1e-10."""
+    nu0 = 27.0 ** 0.25
+    reqs = _mix(k=4, seed=9, nmax=1000, steps_factor=0.5)
+    common = rlb.config_from(8, precision=W.FP64, tau_mode=rlb.RLB_TAU_ETA_OVER_S, with_density=True,
+                             dt_over_dx=0.25, guard_umax=0.9999, nu=nu0,
+                             density_weights=rlb.RLB_DENSW_ISOTROPIC)
+    outs, st = _serve(rlb, common, reqs)
+    assert st.failed == 0
+    for q, out in zip(reqs, outs):
+        w = q.workload(precision=W.FP64, nu=nu0).copy_with(density_weights=W.DENSW_ISOTROPIC)
+        ctx = rlb.context_for_workload(w, precision=W.FP64)
+        ctx.rlb_step(q.steps)
+        ref = ctx.rlb_moments()
+        ctx.close()
+        for a, b in zip(out[0], ref):
+            assert np.array_equal(a, b.ravel())
+        o = oracle_for(w)
+        assert o.step(q.steps) == 0
+        errs = field_errors([a.reshape(w.shape) for a in out[0]], o.fields(),
+                            keys=("eps", "p", "n", "gux"))
+        assert max(errs.values()) <= 1e-10, errs
