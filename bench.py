@@ -161,7 +161,7 @@ def record_traffic(args):
 
 
 def cpu_baseline(workload: str, precision: int, budget_s: float, lattice: str = "extended",
-                 stabilised: bool = False):
+                 stabilised: bool = False, density_weights: int = 0):
     """FP64 CPU oracle on a bounded sample of the same workload recipe."""
     from oracle import oracle as O
     from paper_1302_1125_amd import workloads as W
@@ -187,7 +187,8 @@ def cpu_baseline(workload: str, precision: int, budget_s: float, lattice: str = 
     cfg = O.Config(nx=w.nx, ny=w.ny, nz=w.nz, nu=w.nu, dt=w.dt, euler=(w.collision == 1),
                    tau_mode=w.tau_mode, tau=w.tau, eta_over_s=w.eta_over_s, alpha=w.alpha,
                    with_h=bool(w.with_density), bc=w.bc, face=w.face_states,
-                   guard_umax=w.guard_umax, guard_efloor=w.guard_efloor, basic=(w.lattice == 1))
+                   guard_umax=w.guard_umax, guard_efloor=w.guard_efloor, basic=(w.lattice == 1),
+                   density_weights=density_weights if w.with_density else 0)
 
     def timed(threads, budget):
         """MLUPS of the oracle at `threads` threads: one step, then as many as
@@ -215,6 +216,22 @@ def cpu_baseline(workload: str, precision: int, budget_s: float, lattice: str = 
             "value_1_thread": round(v_one, 4),
             "sample_1_thread": f"{steps1} steps, {total1:.1f} s",
             "cpu_model": cpu_model()}
+
+
+def cpu_baseline_all(budget_s: float):
+    """The FP64 oracle's rate on each configuration of the measurement plan
+    (a bounded sample of each, at all host threads and at one), one JSON
+    line: the 1000-cell shock tube, the gamma = 10 slabs, the 2D shock cloud
+    (512 x 256 sample), the serving requests' tube recipe (8192 cells), the
+    384^3 blast wave (96^3 sample) and the paper's 3D shock cloud (100 x 50 x
+    50 sample)."""
+    out = {}
+    for name in ("shock_tube_1d", "colliding_slabs_1d", "shock_cloud_2d", "blast_wave_3d",
+                 "shock_cloud_3d_weak"):
+        print(f"[cpu] {name}", file=sys.stderr, flush=True)
+        out[name] = cpu_baseline(name, 0, budget_s)
+    print(json.dumps({"metric": "FP64 CPU oracle cell-updates/s per configuration", "unit": "MLUPS",
+                      "kind": "oracle", "configs": out}), flush=True)
 
 
 def cpu_model() -> str:
@@ -426,6 +443,8 @@ def main():
                     help="basic: the same recipe run by the basic model of Sec. II (nu = 1)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-all", action="store_true",
+                    help="time the FP64 oracle on every configuration's sample (no GPU work)")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (counter calibration)")
     ap.add_argument("--record-traffic", nargs=4, metavar=("STEP_FETCH", "STEP_WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -460,6 +479,9 @@ def main():
         if args.copy_probe_gib <= 0:
             raise SystemExit("--record-traffic needs --copy-probe-gib (the size the copy probe ran with)")
         record_traffic(args)
+        return
+    if args.cpu_baseline_all:
+        cpu_baseline_all(args.cpu_seconds)
         return
 
     import torch
@@ -533,7 +555,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(args.workload, precision, args.cpu_seconds, args.lattice, args.stabilised)
+        cpu = cpu_baseline(args.workload, precision, args.cpu_seconds, args.lattice, args.stabilised,
+                           w.density_weights)
 
     out = {
         "metric": "cell-updates/s (MLUPS) & % HBM roofline",
