@@ -48,6 +48,7 @@ struct rlb_ctx {
   void* h[2] = {nullptr, nullptr};
   int cur = 0;
   double* hist = nullptr;
+  double* hist_alt = nullptr;  // 1D extended grids: the second copy for blocked launches
   float* hist32 = nullptr;  // compact previous-step fields (see compact_history)
   uint8_t* obst = nullptr;
   double* face_states = nullptr;   // [6][5]
@@ -130,6 +131,12 @@ bool compact_history(const rlb_config* c) {
          c->lattice == RLB_LATTICE_EXTENDED;
 }
 
+// 1D grids of the extended model step in temporally blocked launches, which
+// move the previous-step fields between two copies (StepParams::hist_out).
+bool blocked_1d(const rlb_config* c) {
+  return c->ny == 1 && c->nz == 1 && c->lattice == RLB_LATTICE_EXTENDED;
+}
+
 uint64_t footprint(const rlb_config* c) {
   const uint64_t nc = static_cast<uint64_t>(c->nx) * c->ny * c->nz;
   const uint64_t ns = static_cast<uint64_t>(rlb::row_pitch(c->nx, c->ny)) * rlb::plane_rows(c->ny) * c->nz;
@@ -138,6 +145,7 @@ uint64_t footprint(const rlb_config* c) {
   uint64_t b = 2 * rlb::Q * ps * elem;            // f, ping-pong
   if (c->with_density) b += 2 * rlb::Q * ps * elem;
   b += 5 * ns * 8;                                // previous-step fields
+  if (blocked_1d(c)) b += 5 * ns * 8;             // their second copy
   if (compact_history(c)) b += 5 * ns * 4;        // and their FP32 form
   b += (nc + 255) / 256 * 5 * 8;                  // reduction partials
   b += 6 * 5 * 8 + 4 * 8 + 8 * 8;                 // face states, counters, sums
@@ -150,6 +158,7 @@ void free_all(rlb_ctx* x) {
     if (x->h[k]) (void)hipFree(x->h[k]);
   }
   if (x->hist) (void)hipFree(x->hist);
+  if (x->hist_alt) (void)hipFree(x->hist_alt);
   if (x->hist32) (void)hipFree(x->hist32);
   if (x->obst) (void)hipFree(x->obst);
   if (x->face_states) (void)hipFree(x->face_states);
@@ -437,6 +446,7 @@ rlb_status rlb_create(const rlb_config* cfg, void* hip_stream, rlb_ctx** out) {
     if (st == RLB_OK && cfg->with_density) st = dalloc(&x->h[k], pop_bytes, "h");
   }
   if (st == RLB_OK) st = dalloc(&x->hist, 5 * sizeof(double) * x->nstore, "fields");
+  if (st == RLB_OK && blocked_1d(cfg)) st = dalloc(&x->hist_alt, 5 * sizeof(double) * x->nstore, "fields");
   if (st == RLB_OK && compact_history(cfg))
     st = dalloc(&x->hist32, 5 * sizeof(float) * x->nstore, "fields (FP32)");
   if (st == RLB_OK) st = dalloc(&x->face_states, 6 * 5 * sizeof(double), "face_states");
@@ -552,7 +562,8 @@ rlb_status rlb_step_async(rlb_ctx* x, int64_t nsteps) {
   const bool wh = x->cfg.with_density != 0;
   const bool eu = x->cfg.collision == RLB_COLL_EULER;
   if (x->act_mask == 1 && x->cfg.lattice == RLB_LATTICE_EXTENDED && x->tb_steps > 1) {
-    // 1D: temporally blocked launches of up to tb_steps steps each
+    // 1D: temporally blocked launches of up to tb_steps steps each; the
+    // previous-step fields alternate between the two copies like f and h
     for (int64_t k = 0; k < nsteps;) {
       const int kb = static_cast<int>(std::min<int64_t>(x->tb_steps, nsteps - k));
       const int cells = rlb::tb_cells_per_tile(kb);
@@ -562,9 +573,13 @@ rlb_status rlb_step_async(rlb_ctx* x, int64_t nsteps) {
       p.f_out = x->f[1 - x->cur];
       p.h_in = x->h[x->cur];
       p.h_out = x->h[1 - x->cur];
+      p.hist = x->hist;
+      p.hist_out = x->hist_alt;
       p.step_index = x->steps;
       const hipError_t e = rlb::launch_step_tb(p, x->fp64, wh, eu, kb, false, grid, x->stream);
       if (e != hipSuccess) return hip_fail(e, "step kernel");
+      std::swap(x->hist, x->hist_alt);
+      x->base.hist = x->hist;
       x->cur = 1 - x->cur;
       x->steps += kb;
       k += kb;

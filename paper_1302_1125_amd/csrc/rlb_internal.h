@@ -59,6 +59,11 @@ struct StepParams {
   const void* h_in;
   void* h_out;
   double* hist;            // [5][ncell]: eps, ux, uy, uz, n of the previous step
+  // Temporally blocked 1D launches (k_step_tb) read hist and write the fields
+  // they leave to hist_out, a second array of the same shape: a workgroup
+  // reads the fields of halo cells that neighbouring workgroups own and
+  // rewrite in the same launch, so the two must not alias.
+  double* hist_out;
   // [5][ncell] FP32: eps, gamma ux, gamma uy, gamma uz, n of the previous step.
   // Used instead of hist by the implicit mixed-precision step of 2D and 3D grids
   // (nullptr otherwise); hist then keeps the initial (obstacle) fields.
@@ -149,7 +154,9 @@ hipError_t launch_sums(const StepParams& p, bool fp64, bool with_h, double* part
 // Temporal blocking of 1D domains (extended lattice): kb in [1, kTbMaxSteps]
 // steps per launch; each workgroup owns tb_cells_per_tile(kb) cells.  seg:
 // p.tiles maps the grid onto segments (tiles of that many cells), else the
-// grid covers the context's 1D domain.
+// grid covers the context's 1D domain.  The previous-step fields move from
+// p.hist to p.hist_out, which must be a distinct array (hipErrorInvalidValue
+// otherwise).
 constexpr int kTbMaxSteps = 16;
 int tb_cells_per_tile(int kb);
 hipError_t launch_step_tb(const StepParams& p, bool fp64, bool with_h, bool euler, int kb,

@@ -1636,7 +1636,10 @@ __global__ __launch_bounds__(kBlock, RLB_ZM_OCC) void k_step_zm(
 // neighbouring regions overlap by 4 KB cells (computed twice, stored once).
 // HBM traffic per step falls by the factor KB.  Every owned cell takes the
 // single-step kernel's arithmetic in the same order; guard events and
-// inadmissible steps are counted by the owner only.  SEG: the region lies in
+// inadmissible steps are counted by the owner only.  The previous-step fields
+// come from hist and go to hist_out (distinct arrays): the halo lanes read
+// fields of cells that the neighbouring workgroups own and rewrite, and a
+// workgroup may start after its neighbour has finished.  SEG: the region lies in
 // one segment of the serving arena (tile table entry (segment, tile)); a
 // segment whose steps are done keeps its state.
 // ---------------------------------------------------------------------------
@@ -1658,8 +1661,8 @@ struct TbOcc {
 template <typename T, bool WH, bool EU, bool SEG>
 __global__ __launch_bounds__(kBlock, (TbOcc<T>::value)) void k_step_tb(
     const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ hin,
-    T* __restrict__ hout, double* __restrict__ hist, const uint8_t* __restrict__ obst,
-    const StepParams P, int KB) {
+    T* __restrict__ hout, const double* __restrict__ hist, double* __restrict__ hist_out,
+    const uint8_t* __restrict__ obst, const StepParams P, int KB) {
   constexpr int R = kBlock;
   constexpr int NA = WH ? 2 * Q : Q;
   __shared__ T lds[NA][R + 2];  // slots R, R + 1: the fixed end states
@@ -1947,11 +1950,11 @@ __global__ __launch_bounds__(kBlock, (TbOcc<T>::value)) void k_step_tb(
       if constexpr (WH) stb_nt(hout + I * S, cl, hc[I]);
     });
     if constexpr (!EU) {
-      stb_nt(hist, cd, pe);
-      stb_nt(hist + NC, cd, pux);
-      stb_nt(hist + 2 * NC, cd, puy);
-      stb_nt(hist + 3 * NC, cd, puz);
-      stb_nt(hist + 4 * NC, cd, pn);
+      stb_nt(hist_out, cd, pe);
+      stb_nt(hist_out + NC, cd, pux);
+      stb_nt(hist_out + 2 * NC, cd, puy);
+      stb_nt(hist_out + 3 * NC, cd, puz);
+      stb_nt(hist_out + 4 * NC, cd, pn);
     }
   }
 }
@@ -2292,7 +2295,7 @@ template <typename T, bool WH, bool EU, bool SEG>
 void tb_t(const StepParams& p, int kb, unsigned grid, hipStream_t s) {
   hipLaunchKernelGGL((k_step_tb<T, WH, EU, SEG>), dim3(grid), dim3(kBlock), 0, s,
                      static_cast<const T*>(p.f_in), static_cast<T*>(p.f_out),
-                     static_cast<const T*>(p.h_in), static_cast<T*>(p.h_out), p.hist,
+                     static_cast<const T*>(p.h_in), static_cast<T*>(p.h_out), p.hist, p.hist_out,
                      SEG ? nullptr : p.obst, p, kb);
 }
 template <typename T, bool SEG>
@@ -2307,6 +2310,7 @@ int tb_cells_per_tile(int kb) { return kBlock - 4 * kb; }
 hipError_t launch_step_tb(const StepParams& p, bool fp64, bool with_h, bool euler, int kb,
                           bool seg, unsigned grid, hipStream_t s) {
   if (kb < 1 || kb > kTbMax || p.lattice != 0) return hipErrorInvalidValue;
+  if (p.hist_out == nullptr || p.hist_out == p.hist) return hipErrorInvalidValue;
   if (grid == 0) return hipSuccess;
   if (fp64) seg ? tb_p<double, true>(p, with_h, euler, kb, grid, s) : tb_p<double, false>(p, with_h, euler, kb, grid, s);
   else seg ? tb_p<float, true>(p, with_h, euler, kb, grid, s) : tb_p<float, false>(p, with_h, euler, kb, grid, s);

@@ -74,7 +74,10 @@ struct rlb_server {
   hipStream_t stream = nullptr;
   void* f[2] = {nullptr, nullptr};
   void* h[2] = {nullptr, nullptr};
-  double* hist = nullptr;
+  // previous-step fields, two copies: blocked launches read one and write the
+  // other (a chunk has an even number of launches and ends on copy 0);
+  // one-step launches update copy 0 in place
+  double* hist[2] = {nullptr, nullptr};
   rlb::SegDesc* d_segs = nullptr;
   rlb::SegDesc* h_segs = nullptr;  // pinned
   int2* d_tiles = nullptr;
@@ -125,7 +128,7 @@ namespace {
 
 uint64_t bytes_per_cell(const rlb_config& c) {
   const uint64_t e = c.precision == RLB_FP64 ? 8 : 4;
-  return 2 * rlb::Q * e * (c.with_density ? 2 : 1) + 5 * 8;
+  return 2 * rlb::Q * e * (c.with_density ? 2 : 1) + 2 * 5 * 8;
 }
 
 long long footprint_cells(int n) { return round_up(static_cast<long long>(n) + 2, kAlign); }
@@ -153,7 +156,8 @@ void free_server(rlb_server* s) {
     if (s->f[k]) (void)hipFree(s->f[k]);
     if (s->h[k]) (void)hipFree(s->h[k]);
   }
-  void* dev[] = {s->hist, s->d_segs, s->d_tiles, s->d_gstep, s->d_bad, s->d_guard, s->d_face, s->d_out};
+  void* dev[] = {s->hist[0], s->hist[1], s->d_segs, s->d_tiles, s->d_gstep,
+                 s->d_bad,     s->d_guard,   s->d_face, s->d_out};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   void* host[] = {s->h_segs, s->h_tiles, s->h_gstep, s->h_guard, s->h_bad, s->h_reset, s->h_face,
@@ -209,6 +213,10 @@ hipError_t graph_for(rlb_server* s, unsigned grid, hipGraphExec_t* out) {
     p.f_out = s->f[(j + 1) % 2];
     p.h_in = s->h[j % 2];
     p.h_out = s->h[(j + 1) % 2];
+    if (s->tb > 1) {
+      p.hist = s->hist[j % 2];
+      p.hist_out = s->hist[(j + 1) % 2];
+    }
     p.step_in_chunk = j * s->tb;
     e = s->tb > 1 ? rlb::launch_step_tb(p, s->fp64, s->with_h, s->euler, s->tb, true, grid, s->stream)
                   : rlb::launch_seg_step(p, s->fp64, s->with_h, s->euler, grid, s->stream);
@@ -251,7 +259,7 @@ hipError_t admit(rlb_server* s) {
     hipError_t e = hipSuccess;
     for (int k = 0; k < 5 && e == hipSuccess; ++k) {
       if (k == 4 && !s->with_h) continue;
-      e = hipMemcpyAsync(s->hist + k * s->cap + at + 1, r.io.data() + k * r.n, sizeof(double) * r.n,
+      e = hipMemcpyAsync(s->hist[0] + k * s->cap + at + 1, r.io.data() + k * r.n, sizeof(double) * r.n,
                          hipMemcpyHostToDevice, s->stream);
     }
     if (e != hipSuccess) return e;
@@ -552,7 +560,7 @@ rlb_status rlb_server_create(const rlb_config* common, uint64_t budget_bytes, in
     e = dmalloc(&s->f[k], pop);
     if (e == hipSuccess && s->with_h) e = dmalloc(&s->h[k], pop);
   }
-  if (e == hipSuccess) e = dmalloc(&s->hist, 5 * sizeof(double) * cap);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = dmalloc(&s->hist[k], 5 * sizeof(double) * cap);
   if (e == hipSuccess) e = dmalloc(&s->d_segs, sizeof(rlb::SegDesc) * s->max_slots);
   if (e == hipSuccess) e = hmalloc(&s->h_segs, sizeof(rlb::SegDesc) * s->max_slots);
   if (e == hipSuccess) e = dmalloc(&s->d_tiles, sizeof(int2) * s->max_tiles);
@@ -583,7 +591,7 @@ rlb_status rlb_server_create(const rlb_config* common, uint64_t budget_bytes, in
   s->base.ny = s->base.nz = 1;
   s->base.px = s->base.nx;
   s->base.py = 1;
-  s->base.hist = s->hist;
+  s->base.hist = s->hist[0];
   s->base.obst = nullptr;
   s->base.segs = s->d_segs;
   s->base.tiles = s->d_tiles;

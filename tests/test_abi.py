@@ -76,12 +76,18 @@ def test_host_side_validation_without_device():
     eu = rlb.config_from(128, 64, 32, precision=rlb.RLB_MIXED, with_density=True,
                          collision=rlb.RLB_COLL_EULER)
     assert rlb.rlb_footprint_bytes(eu) == fp - n * 5 * 4
-    # FP64 and 1D contexts keep the previous-step fields in FP64 only
+    # FP64 and 1D contexts keep the previous-step fields in FP64 only; 1D
+    # contexts hold two copies of them (temporally blocked launches read one
+    # and write the other)
     f64 = rlb.config_from(128, 64, 32, precision=rlb.RLB_FP64, with_density=True)
     assert n * (4 * 19 * 8 + 5 * 8) <= rlb.rlb_footprint_bytes(f64) <= n * (4 * 19 * 8 + 5 * 8) * 1.01 + 4096
     one = rlb.config_from(1 << 16, precision=rlb.RLB_MIXED, with_density=True)
-    m1 = 1 << 16
-    assert m1 * (4 * 19 * 4 + 5 * 8) <= rlb.rlb_footprint_bytes(one) <= m1 * (4 * 19 * 4 + 5 * 8) * 1.01 + 4096
+    m1, pc1 = 1 << 16, 4 * 19 * 4 + 2 * 5 * 8
+    assert m1 * pc1 <= rlb.rlb_footprint_bytes(one) <= m1 * pc1 * 1.01 + 4096
+    # a serving request: f and h (two copies each) and two copies of the
+    # previous-step fields per cell, its n cells and two ghost cells rounded
+    # up to the arena's unit of 64 cells
+    assert rlb.rlb_request_footprint_bytes(m, 1000) == 1024 * (4 * 19 * 4 + 2 * 5 * 8)
     bad = rlb.config_from(8, 1, 4)
     assert rlb.rlb_footprint_bytes(bad) == 0
 

@@ -83,6 +83,32 @@ def test_tb_equals_single_step_fp64(rlb, tb, nx, bc):
     _same(a, b)
 
 
+def test_tb_with_more_workgroups_than_are_resident(rlb):
+    """2.1 M cells (a 300-cell smooth random state repeated 7000 times,
+    periodic; 9375 workgroups per launch at 8 steps, more than the GPU holds
+    at once, so some workgroups start after their neighbours have finished).
+    The halo lanes of a workgroup take the previous-step fields of cells that
+    its neighbours own; those must be the fields the launch started with, so
+    the blocked launches agree with one step per launch cell by cell (FP64,
+    24 steps).  Fields of a later step would move the cells near the tile
+    edges by ~1e-4 on this state."""
+    base = _smooth_1d(300, 5, (0, 0))
+    reps = 7000
+    w = base.copy_with(nx=300 * reps)
+    for k in ("eps", "ux", "uy", "uz", "n"):
+        setattr(w, k, np.tile(getattr(base, k), (1, 1, reps)))
+    a, sa, _ = _run(rlb, w, 24, 8)
+    b, sb, _ = _run(rlb, w, 24, 1)
+    for x, y in zip(a, b):
+        scale = np.maximum(np.abs(y), 1.0)
+        d = float(np.max(np.abs(x - y) / scale))
+        assert d <= 1e-12, d
+    # every 300-cell block takes the same arithmetic on the same values
+    for x in a:
+        blocks = x.reshape(reps, 300)
+        np.testing.assert_allclose(blocks, np.broadcast_to(blocks[0], blocks.shape), rtol=1e-13, atol=1e-15)
+
+
 def test_tb_guarded_slabs_equal_single_step(rlb):
     """Colliding slabs at gamma = 10 with density and the guard on (FP64):
     event counts identical, fields within the FP64 parity bar.  The guarded
