@@ -1435,6 +1435,10 @@ __global__ __launch_bounds__(kBlock, RLB_ZM_OCC) void k_step_zm(
         }
       });
     }
+    // the next plane's centres without a window and its previous-step
+    // fields (this plane's were copied out above); issued before the
+    // recovery, measured 0.5% faster than after it
+    if (z + 1 < ze) load_centres(z + 1);
     if (RLB_ZM_PRIO) __builtin_amdgcn_s_setprio(0);
     const double pg2 = 1.0 + (gxp * gxp + gyp * gyp + gzp * gzp);
     const double ig = 1.0 / sqrt(pg2);
@@ -1473,7 +1477,6 @@ __global__ __launch_bounds__(kBlock, RLB_ZM_OCC) void k_step_zm(
       pst<3, kNT>(Qh, cbs, qb, static_cast<float>(F.gam * F.uz));
       pst<4, kNT>(Qh, cbs, qb, static_cast<float>(F.n));
     }
-    if (z + 1 < ze) load_centres(z + 1);
     const unsigned hr = rxy + static_cast<unsigned>(z) * rst;
     const unsigned hx = xxy + static_cast<unsigned>(z) * xst;
     const int hcol = lane < 2 ? lane : 64 + lane;
