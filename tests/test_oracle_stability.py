@@ -518,20 +518,24 @@ def test_rusanov_flux_stabilises_the_euler_mode_only(oracle_mod):
     the gamma = 10 slabs' parameters (growth <= 1e-9 per step, against 0.03
     - 0.09 with the upwind flux).  The implicit (viscous) update is not
     cured: at tau = 0.55 - 3 it still grows by 1.3e-2 - 2e-2 per step at
-    |u| = 0.99, and so does the plain implicit BGK update without the history
-    extrapolation, so the growth comes from relaxing toward this equilibrium
-    with finite tau, not from the flux splitting alone."""
+    |u| = 0.99, and so do the plain implicit BGK update without the history
+    extrapolation and a collision after streaming toward the equilibrium of
+    the post-streaming moments ((1 + omega J K) S / (1 + omega)), so the
+    growth comes from relaxing toward this equilibrium with finite tau, not
+    from the flux splitting or the time discretisation."""
     O = oracle_mod
     p = _speeds(O, NU0)
     dt, alpha = 0.25, 0.0048
     kappa = NU0 * NU0 / math.sqrt(27.0) * alpha * dt
 
-    def matrix(u, tau, theta, lin, rusanov=True, history=True):
+    def matrix(u, tau, theta, lin, rusanov=True, history=True, post=False):
         K, J, _, _ = lin
         S = np.diag(_stream_rusanov(p, dt, theta, kappa) if rusanov else _stream(p, dt, theta, kappa))
         if tau is None:
             return J @ K @ S
         om = NU0 * NU0 * dt / (math.sqrt(27.0) * tau)
+        if post:
+            return (np.eye(19) + om * J @ K) @ S / (1.0 + om)
         if not history:
             return (S + om * J @ K) / (1.0 + om)
         G = np.zeros((23, 23), complex)
@@ -549,3 +553,4 @@ def test_rusanov_flux_stabilises_the_euler_mode_only(oracle_mod):
     for tau in (0.55, 1.0, 3.0):
         assert _growth(lambda t: matrix(0.99, tau, t, lin), 61) > 1e-2, tau
         assert _growth(lambda t: matrix(0.99, tau, t, lin, history=False), 61) > 1e-2, tau
+        assert _growth(lambda t: matrix(0.99, tau, t, lin, post=True), 61) > 1e-2, tau
