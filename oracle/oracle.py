@@ -21,6 +21,7 @@ Q = 19
 BC_PERIODIC, BC_FIXED, BC_OUTFLOW = 0, 1, 2
 TAU_UNIFORM, TAU_ETA_OVER_S = 0, 1
 DENSW_PAPER, DENSW_ISOTROPIC = 0, 1
+FLUX_MINMOD, FLUX_RUSANOV = 0, 1
 
 _lib = None
 
@@ -45,7 +46,7 @@ class _Cfg(ctypes.Structure):
         ("alpha", ctypes.c_double), ("with_h", ctypes.c_int),
         ("bc", ctypes.c_int * 6), ("face", (ctypes.c_double * 5) * 6),
         ("guard_umax", ctypes.c_double), ("guard_efloor", ctypes.c_double),
-        ("basic", ctypes.c_int), ("dens_w", ctypes.c_int),
+        ("basic", ctypes.c_int), ("dens_w", ctypes.c_int), ("flux", ctypes.c_int),
     ]
 
 
@@ -155,6 +156,7 @@ class Config:
     guard_efloor: float = 1e-10
     basic: bool = False  # the basic model of Sec. II (dt, euler, alpha, guard unused/off)
     density_weights: int = 0  # DENSW_PAPER | DENSW_ISOTROPIC (extended set)
+    flux: int = 0  # FLUX_MINMOD (Eqs. (47)-(53)) | FLUX_RUSANOV (extended set)
 
     def _c(self) -> _Cfg:
         c = _Cfg()
@@ -171,6 +173,7 @@ class Config:
         c.guard_umax, c.guard_efloor = self.guard_umax, self.guard_efloor
         c.basic = int(self.basic)
         c.dens_w = int(self.density_weights)
+        c.flux = int(self.flux)
         return c
 
 

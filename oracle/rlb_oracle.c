@@ -323,6 +323,8 @@ orc_state* orc_create(const orc_config* cfg) {
   if (cfg->basic && (cfg->euler || cfg->alpha != 0.0 || cfg->guard_umax > 0 || cfg->with_h))
     return NULL;
   if (cfg->dens_w != ORC_DENSW_PAPER && cfg->dens_w != ORC_DENSW_ISOTROPIC) return NULL;
+  if (cfg->flux != ORC_FLUX_MINMOD && cfg->flux != ORC_FLUX_RUSANOV) return NULL;
+  if (cfg->flux == ORC_FLUX_RUSANOV && cfg->basic) return NULL;
   if (cfg->dens_w == ORC_DENSW_ISOTROPIC &&
       (cfg->basic || 13.0 / (cfg->nu * cfg->nu) < 17.0 / 24.0))
     return NULL; /* extended set only; w'_0 >= 0 needs c_a^2 >= 17/24 */
@@ -468,12 +470,31 @@ static inline double at_off(const orc_state* S, const double* arr_i, int x,
   return arr_i[pidx(S, c[0], c[1], c[2])];
 }
 
+/* Rusanov (local Lax-Friedrichs) interface flux, first order -- beyond the
+   paper: h = 1/2 p (f(X) + f(X + e_a)) - 1/2 s (f(X + e_a) - f(X)) with one
+   dissipation speed s for every population, moving or not.  With s = xi^0 =
+   c_t/c_0 (the speed of light in the units of p) the moments of the update
+   are the Rusanov scheme of the macroscopic equations; the divergence of h
+   is returned directly. */
+static inline double rusanov_div(double p, double s, double fm1, double f0,
+                                 double fp1) {
+  return 0.5 * p * (fp1 - fm1) - 0.5 * s * ((fp1 - f0) - (f0 - fm1));
+}
+
 /* Sum over axes of [h_i^a(x) - h_i^a(x - e_a)] / dx: the divergence of the
    limited flux of p_i^a f_i between the interfaces x +- 1/2 (Eq. (47),
-   conservative reading), with p_i^a = xi_i^a. */
+   conservative reading), with p_i^a = xi_i^a; or of the Rusanov flux above
+   (ORC_FLUX_RUSANOV, every population along every axis). */
 static double div_flux(const orc_state* S, const double* arr_i, int i, int x,
                        int y, int z) {
   double d = 0.0;
+  if (S->cfg.flux == ORC_FLUX_RUSANOV) {
+    const double s = S->L.xi[i][0];
+    for (int a = 0; a < 3; ++a)
+      d += rusanov_div(S->L.xi[i][1 + a], s, at_off(S, arr_i, x, y, z, a, -1),
+                       arr_i[pidx(S, x, y, z)], at_off(S, arr_i, x, y, z, a, +1));
+    return d;
+  }
   for (int a = 0; a < 3; ++a) {
     const double p = S->L.xi[i][1 + a];
     if (p == 0.0) continue;

@@ -46,9 +46,13 @@ typedef struct {
   int dens_w;         /* density weights w'_i of Eq. (58): ORC_DENSW_PAPER
                          (Eqs. (59)-(60)) or ORC_DENSW_ISOTROPIC (beyond the
                          paper, see make_lattice); extended set only          */
+  int flux;           /* streaming flux: ORC_FLUX_MINMOD (Eqs. (47)-(53)) or
+                         ORC_FLUX_RUSANOV (beyond the paper, see div_flux);
+                         extended set only                                    */
 } orc_config;
 
 enum { ORC_DENSW_PAPER = 0, ORC_DENSW_ISOTROPIC = 1 };
+enum { ORC_FLUX_MINMOD = 0, ORC_FLUX_RUSANOV = 1 };
 
 typedef struct orc_state orc_state;
 

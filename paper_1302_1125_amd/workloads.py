@@ -28,6 +28,7 @@ COLL_IMPLICIT, COLL_EULER = 0, 1
 TAU_UNIFORM, TAU_ETA_OVER_S = 0, 1
 LATTICE_EXTENDED, LATTICE_BASIC = 0, 1
 DENSW_PAPER, DENSW_ISOTROPIC = 0, 1  # density weights of Eq. (58): Eqs. (59)-(60) | isotropic
+FLUX_MINMOD, FLUX_RUSANOV = 0, 1  # streaming flux: Eqs. (47)-(53) | first-order Rusanov (1D)
 
 
 @dataclass
@@ -52,6 +53,7 @@ class Workload:
     guard_efloor: float = 1e-10
     lattice: int = LATTICE_EXTENDED
     density_weights: int = DENSW_PAPER
+    flux: int = FLUX_MINMOD
     eps: Optional[np.ndarray] = None
     ux: Optional[np.ndarray] = None
     uy: Optional[np.ndarray] = None

@@ -11,7 +11,7 @@ def oracle_for(w, **over):
                    tau_mode=w.tau_mode, tau=w.tau, eta_over_s=w.eta_over_s, alpha=w.alpha,
                    with_h=bool(w.with_density), bc=list(w.bc), face=[list(s) for s in w.face_states],
                    guard_umax=w.guard_umax, guard_efloor=w.guard_efloor,
-                   basic=(w.lattice == 1), density_weights=w.density_weights)
+                   basic=(w.lattice == 1), density_weights=w.density_weights, flux=w.flux)
     for k, v in over.items():
         setattr(cfg, k, v)
     o = O.Oracle(cfg)
