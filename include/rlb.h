@@ -57,6 +57,7 @@ typedef enum {
 } rlb_status;
 
 enum { RLB_FP64 = 0, RLB_MIXED = 1 };              /* storage/arith precision */
+enum { RLB_FLUX_MINMOD = 0, RLB_FLUX_RUSANOV = 1 }; /* Eqs. (47)-(53) | Rusanov */
 enum { RLB_COLL_IMPLICIT = 0, RLB_COLL_EULER = 1 }; /* Eq. (57) | Sec. III     */
 enum { RLB_TAU_UNIFORM = 0, RLB_TAU_ETA_OVER_S = 1 };
 enum { RLB_BC_PERIODIC = 0, RLB_BC_FIXED = 1, RLB_BC_OUTFLOW = 2 };
@@ -137,6 +138,21 @@ typedef struct {
                            the density part up to |u| = 0.995 at dt 0.25
                            (1D) and 0.15 (3D).  Extended lattice only, and
                            nu <= sqrt(13 * 24/17) = 4.28.                   */
+  int32_t flux;         /* streaming flux of the extended lattice.
+                           RLB_FLUX_MINMOD (default): the minmod-limited
+                           upwind flux of Eqs. (47)-(53).
+                           RLB_FLUX_RUSANOV (not in the paper): the
+                           first-order Rusanov (local Lax-Friedrichs) flux
+                           1/2 p (f_L + f_R) - 1/2 s (f_R - f_L) with the
+                           speed of light as the dissipation speed s of every
+                           population, moving or not; the moments of the
+                           update are then the Rusanov scheme of the fluid
+                           equations, and in the Euler mode
+                           (RLB_COLL_EULER) an admissible state stays
+                           admissible (e.g. the gamma = 10 colliding slabs
+                           run without the guard).  The implicit update is
+                           not made admissible by it.  1D grids only
+                           (ny = nz = 1); not in the server.               */
 } rlb_config;
 
 typedef struct {

@@ -99,6 +99,9 @@ rlb_status validate(const rlb_config* c) {
   if (c->density_weights == RLB_DENSW_ISOTROPIC &&
       (c->lattice != RLB_LATTICE_EXTENDED || 13.0 / (c->nu * c->nu) < 17.0 / 24.0))
     return fail(RLB_E_INVALID_ARG, "isotropic density weights: extended lattice, nu <= 4.28");
+  if (c->flux != RLB_FLUX_MINMOD && c->flux != RLB_FLUX_RUSANOV) return fail(RLB_E_INVALID_ARG, "flux");
+  if (c->flux == RLB_FLUX_RUSANOV && (c->lattice != RLB_LATTICE_EXTENDED || c->ny != 1 || c->nz != 1))
+    return fail(RLB_E_INVALID_ARG, "Rusanov flux: extended lattice, 1D grids (ny = nz = 1)");
   if (c->tau_mode == RLB_TAU_UNIFORM && !(c->tau > 0 && std::isfinite(c->tau)))
     return fail(RLB_E_INVALID_ARG, "tau must be > 0");
   if (!(c->eta_over_s >= 0 && std::isfinite(c->eta_over_s))) return fail(RLB_E_INVALID_ARG, "eta_over_s >= 0");
@@ -299,6 +302,7 @@ void fill_constants(const rlb_config& c, rlb::StepParams& p) {
   p.tau = c.tau;
   p.nu2_etas = nu * nu * c.eta_over_s;
   p.tau_mode = c.tau_mode;
+  p.flux = c.flux == RLB_FLUX_RUSANOV ? rlb::kFluxRusanov : rlb::kFluxMinmod;
   p.guard = c.guard_umax > 0 ? 1 : 0;
   if (p.guard) {
     const double um = c.guard_umax, u1 = 1.0 - 2.0 * (1.0 - um);
@@ -561,7 +565,8 @@ rlb_status rlb_step_async(rlb_ctx* x, int64_t nsteps) {
   if (st != RLB_OK) return st;
   const bool wh = x->cfg.with_density != 0;
   const bool eu = x->cfg.collision == RLB_COLL_EULER;
-  if (x->act_mask == 1 && x->cfg.lattice == RLB_LATTICE_EXTENDED && x->tb_steps > 1) {
+  const bool rusanov = x->cfg.flux == RLB_FLUX_RUSANOV;  // built in the blocked step only
+  if (x->act_mask == 1 && x->cfg.lattice == RLB_LATTICE_EXTENDED && (x->tb_steps > 1 || rusanov)) {
     // 1D: temporally blocked launches of up to tb_steps steps each; the
     // previous-step fields alternate between the two copies like f and h
     for (int64_t k = 0; k < nsteps;) {

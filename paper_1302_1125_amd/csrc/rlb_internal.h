@@ -52,6 +52,11 @@ inline long long population_stride(long long ncell) {
 // below 2^31.  The serving arena obeys the same limit.
 constexpr long long kMaxCells = (1ll << 28) - 128;
 
+// Streaming flux of the extended model: the paper's minmod-limited upwind
+// flux, or the first-order Rusanov flux (beyond the paper; 1D, blocked step).
+constexpr int kFluxMinmod = 0;
+constexpr int kFluxRusanov = 1;
+
 // Everything a step kernel needs, passed by value (kernarg segment).
 struct StepParams {
   const void* f_in;
@@ -108,6 +113,7 @@ struct StepParams {
   double tau;       // uniform relaxation time
   double nu2_etas;  // nu^2 * eta/s
   int tau_mode;     // 0 uniform, 1 eta/s
+  int flux;         // kFluxMinmod (Eqs. (47)-(53)) or kFluxRusanov (k_step_tb only)
   int guard;        // 0/1
   double m1, mmax, efloor;
   double gmax;      // Lorentz factor at m_max (bounds gamma of projected moments)
@@ -156,7 +162,8 @@ hipError_t launch_sums(const StepParams& p, bool fp64, bool with_h, double* part
 // p.tiles maps the grid onto segments (tiles of that many cells), else the
 // grid covers the context's 1D domain.  The previous-step fields move from
 // p.hist to p.hist_out, which must be a distinct array (hipErrorInvalidValue
-// otherwise).
+// otherwise).  p.flux == kFluxRusanov selects the Rusanov flux (not in
+// segment mode).
 constexpr int kTbMaxSteps = 16;
 int tb_cells_per_tile(int kb);
 hipError_t launch_step_tb(const StepParams& p, bool fp64, bool with_h, bool euler, int kb,

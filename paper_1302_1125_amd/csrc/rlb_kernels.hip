@@ -1716,7 +1716,20 @@ template <typename T>
 struct TbOcc {
   static constexpr int value = sizeof(T) == 4 ? RLB_TB_OCC_F32 : RLB_TB_OCC_F64;
 };
-template <typename T, bool WH, bool EU, bool SEG>
+// Rusanov (local Lax-Friedrichs) flux along x, first order -- beyond the
+// paper: the interface flux 1/2 p (f_L + f_R) - 1/2 s (f_R - f_L) with one
+// dissipation speed s for every population, moving or not (the speed of
+// light), so that the moments of the update are the Rusanov scheme of the
+// fluid equations.  cx = dt p (the population's Courant number along x),
+// cs = dt s.  dD: dt times the flux divergence; nsum: the Laplacian's
+// neighbour sum.
+template <typename T>
+__device__ __forceinline__ void rusanov_terms(T fm, T f0, T fp, T cx, T cs, T& dD, T& nsum) {
+  dD = T(0.5) * cx * (fp - fm) - T(0.5) * cs * ((fp - f0) - (f0 - fm));
+  nsum = fm + fp;
+}
+
+template <typename T, bool WH, bool EU, bool SEG, bool RUS>
 __global__ __launch_bounds__(kBlock, (TbOcc<T>::value)) void k_step_tb(
     const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ hin,
     T* __restrict__ hout, const double* __restrict__ hist, double* __restrict__ hist_out,
@@ -1818,6 +1831,7 @@ __global__ __launch_bounds__(kBlock, (TbOcc<T>::value)) void k_step_tb(
     pn = ldb(hist + 4 * NC, cd);
   }
   const T dtv = static_cast<T>(P.dtv);
+  const T dtc = static_cast<T>(P.dtv * sqrt(27.0 / 13.0));  // dt times the speed of light
   constexpr T NA2 = T(2);
 
   for (int st = 0; st < KB; ++st) {
@@ -1854,10 +1868,14 @@ __global__ __launch_bounds__(kBlock, (TbOcc<T>::value)) void k_step_tb(
       double m0 = 0.0, mx = 0.0, my = 0.0, mz = 0.0, mh = 0.0;
       static_for<0, Q>([&](auto I) {
         constexpr Vel e = vel(I);
-        Sten<T> sf;
-        sten(I, I, I != 0, sf);
         T dD, ns;
-        stream_terms<T, 1, I, (I != 0)>(sf, fc[I], dtv, dD, ns);
+        if constexpr (RUS) {
+          rusanov_terms(lds[I][pos[1]], fc[I], lds[I][pos[2]], dtv * T(e.x), dtc, dD, ns);
+        } else {
+          Sten<T> sf;
+          sten(I, I, I != 0, sf);
+          stream_terms<T, 1, I, (I != 0)>(sf, fc[I], dtv, dD, ns);
+        }
         T v;
         if constexpr (I != 0) v = (fc[I] - dD) + kap * (ns - NA2 * fc[I]);
         else v = fc[I] - dD;
@@ -1867,10 +1885,14 @@ __global__ __launch_bounds__(kBlock, (TbOcc<T>::value)) void k_step_tb(
         if constexpr (e.y != 0) my += double(e.y) * vd;
         if constexpr (e.z != 0) mz += double(e.z) * vd;
         if constexpr (WH) {
-          Sten<T> sh;
-          sten(I, Q + I, false, sh);
           T dH, nh;
-          stream_terms<T, 1, I, false>(sh, hc[I], dtv, dH, nh);
+          if constexpr (RUS) {
+            rusanov_terms(lds[Q + I][pos[1]], hc[I], lds[Q + I][pos[2]], dtv * T(e.x), dtc, dH, nh);
+          } else {
+            Sten<T> sh;
+            sten(I, Q + I, false, sh);
+            stream_terms<T, 1, I, false>(sh, hc[I], dtv, dH, nh);
+          }
           mh += static_cast<double>(hc[I] - dH);
         }
       });
@@ -1937,10 +1959,14 @@ __global__ __launch_bounds__(kBlock, (TbOcc<T>::value)) void k_step_tb(
       T gE = T(0), gX = T(0), gY = T(0), gZ = T(0), gN = T(0), gA = T(0), gAh = T(0);
       static_for<0, Q>([&](auto I) {
         constexpr Vel e = vel(I);
-        Sten<T> sf;
-        sten(I, I, I != 0, sf);
         T dD, ns;
-        stream_terms<T, 1, I, (I != 0)>(sf, fc[I], dtv, dD, ns);
+        if constexpr (RUS) {
+          rusanov_terms(lds[I][pos[1]], fc[I], lds[I][pos[2]], dtv * T(e.x), dtc, dD, ns);
+        } else {
+          Sten<T> sf;
+          sten(I, I, I != 0, sf);
+          stream_terms<T, 1, I, (I != 0)>(sf, fc[I], dtv, dD, ns);
+        }
         T v = (fc[I] - dD) * tinv + static_cast<T>(weight(I)) * bracket<I>(Kt);
         if constexpr (I != 0) v += kinv * (ns - NA2 * fc[I]);
         fc[I] = v;
@@ -1950,10 +1976,14 @@ __global__ __launch_bounds__(kBlock, (TbOcc<T>::value)) void k_step_tb(
         if constexpr (e.y != 0) gY += T(e.y) * v;
         if constexpr (e.z != 0) gZ += T(e.z) * v;
         if constexpr (WH) {
-          Sten<T> sh;
-          sten(I, Q + I, false, sh);
           T dH, nh;
-          stream_terms<T, 1, I, false>(sh, hc[I], dtv, dH, nh);
+          if constexpr (RUS) {
+            rusanov_terms(lds[Q + I][pos[1]], hc[I], lds[Q + I][pos[2]], dtv * T(e.x), dtc, dH, nh);
+          } else {
+            Sten<T> sh;
+            sten(I, Q + I, false, sh);
+            stream_terms<T, 1, I, false>(sh, hc[I], dtv, dH, nh);
+          }
           const T wpi = I == 0 ? wp[0] : (I <= 6 ? wp[1] : wp[2]);
           const T hv = (hc[I] - dH) * tinv + wpi * bracket<I>(Ht);
           hc[I] = hv;
@@ -2349,17 +2379,19 @@ hipError_t launch_step(const StepParams& p, bool fp64, int act_mask, bool with_h
 }
 
 namespace {
-template <typename T, bool WH, bool EU, bool SEG>
+template <typename T, bool WH, bool EU, bool SEG, bool RUS>
 void tb_t(const StepParams& p, int kb, unsigned grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_step_tb<T, WH, EU, SEG>), dim3(grid), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL((k_step_tb<T, WH, EU, SEG, RUS>), dim3(grid), dim3(kBlock), 0, s,
                      static_cast<const T*>(p.f_in), static_cast<T*>(p.f_out),
                      static_cast<const T*>(p.h_in), static_cast<T*>(p.h_out), p.hist, p.hist_out,
                      SEG ? nullptr : p.obst, p, kb);
 }
-template <typename T, bool SEG>
+template <typename T, bool SEG, bool RUS>
 void tb_p(const StepParams& p, bool with_h, bool euler, int kb, unsigned grid, hipStream_t s) {
-  if (with_h) euler ? tb_t<T, true, true, SEG>(p, kb, grid, s) : tb_t<T, true, false, SEG>(p, kb, grid, s);
-  else euler ? tb_t<T, false, true, SEG>(p, kb, grid, s) : tb_t<T, false, false, SEG>(p, kb, grid, s);
+  if (with_h)
+    euler ? tb_t<T, true, true, SEG, RUS>(p, kb, grid, s) : tb_t<T, true, false, SEG, RUS>(p, kb, grid, s);
+  else
+    euler ? tb_t<T, false, true, SEG, RUS>(p, kb, grid, s) : tb_t<T, false, false, SEG, RUS>(p, kb, grid, s);
 }
 }  // namespace
 
@@ -2369,9 +2401,17 @@ hipError_t launch_step_tb(const StepParams& p, bool fp64, bool with_h, bool eule
                           bool seg, unsigned grid, hipStream_t s) {
   if (kb < 1 || kb > kTbMax || p.lattice != 0) return hipErrorInvalidValue;
   if (p.hist_out == nullptr || p.hist_out == p.hist) return hipErrorInvalidValue;
+  if (p.flux != kFluxMinmod && (seg || p.flux != kFluxRusanov)) return hipErrorInvalidValue;
   if (grid == 0) return hipSuccess;
-  if (fp64) seg ? tb_p<double, true>(p, with_h, euler, kb, grid, s) : tb_p<double, false>(p, with_h, euler, kb, grid, s);
-  else seg ? tb_p<float, true>(p, with_h, euler, kb, grid, s) : tb_p<float, false>(p, with_h, euler, kb, grid, s);
+  if (p.flux == kFluxRusanov)
+    fp64 ? tb_p<double, false, true>(p, with_h, euler, kb, grid, s)
+         : tb_p<float, false, true>(p, with_h, euler, kb, grid, s);
+  else if (fp64)
+    seg ? tb_p<double, true, false>(p, with_h, euler, kb, grid, s)
+        : tb_p<double, false, false>(p, with_h, euler, kb, grid, s);
+  else
+    seg ? tb_p<float, true, false>(p, with_h, euler, kb, grid, s)
+        : tb_p<float, false, false>(p, with_h, euler, kb, grid, s);
   return hipGetLastError();
 }
 

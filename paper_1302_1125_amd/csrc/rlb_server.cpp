@@ -515,6 +515,7 @@ rlb_status rlb_server_create(const rlb_config* common, uint64_t budget_bytes, in
   if (st != RLB_OK) return st;
   if (c.lattice != RLB_LATTICE_EXTENDED)
     return rlb_set_error(RLB_E_INVALID_ARG, "the server runs the extended lattice only");
+  if (c.flux != RLB_FLUX_MINMOD) return rlb_set_error(RLB_E_INVALID_ARG, "the server runs the minmod flux only");
   if (chunk_steps < 2 || chunk_steps % 2 != 0 || chunk_steps > 4096)
     return rlb_set_error(RLB_E_INVALID_ARG, "chunk_steps must be even, 2..4096");
   const uint64_t bpc = bytes_per_cell(c);

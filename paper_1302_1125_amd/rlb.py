@@ -29,6 +29,7 @@ RLB_TAU_UNIFORM, RLB_TAU_ETA_OVER_S = 0, 1
 RLB_BC_PERIODIC, RLB_BC_FIXED, RLB_BC_OUTFLOW = 0, 1, 2
 RLB_LATTICE_EXTENDED, RLB_LATTICE_BASIC = 0, 1
 RLB_DENSW_PAPER, RLB_DENSW_ISOTROPIC = 0, 1
+RLB_FLUX_MINMOD, RLB_FLUX_RUSANOV = 0, 1
 
 EXPORTED = [
     "rlb_config_default", "rlb_create", "rlb_init_fields", "rlb_step", "rlb_step_async",
@@ -47,7 +48,7 @@ class rlb_config(ctypes.Structure):
         ("eta_over_s", ctypes.c_double), ("alpha", ctypes.c_double),
         ("bc", ctypes.c_int32 * 6), ("face_states", (ctypes.c_double * 5) * 6),
         ("guard_umax", ctypes.c_double), ("guard_efloor", ctypes.c_double),
-        ("lattice", ctypes.c_int32), ("density_weights", ctypes.c_int32),
+        ("lattice", ctypes.c_int32), ("density_weights", ctypes.c_int32), ("flux", ctypes.c_int32),
     ]
 
 
@@ -136,7 +137,8 @@ def config_from(nx, ny=1, nz=1, precision=RLB_FP64, collision=RLB_COLL_IMPLICIT,
                 tau_mode=RLB_TAU_UNIFORM, with_density=False, nu=27.0 ** 0.25, dt_over_dx=0.25,
                 tau=1.0, eta_over_s=0.0, alpha=0.0, bc: Sequence[int] = (0,) * 6,
                 face_states=None, guard_umax=0.0, guard_efloor=1e-10,
-                lattice=RLB_LATTICE_EXTENDED, density_weights=RLB_DENSW_PAPER) -> rlb_config:
+                lattice=RLB_LATTICE_EXTENDED, density_weights=RLB_DENSW_PAPER,
+                flux=RLB_FLUX_MINMOD) -> rlb_config:
     c = rlb_config_default()
     c.nx, c.ny, c.nz = int(nx), int(ny), int(nz)
     c.precision, c.collision, c.tau_mode = int(precision), int(collision), int(tau_mode)
@@ -151,6 +153,7 @@ def config_from(nx, ny=1, nz=1, precision=RLB_FP64, collision=RLB_COLL_IMPLICIT,
     c.guard_umax, c.guard_efloor = float(guard_umax), float(guard_efloor)
     c.lattice = int(lattice)
     c.density_weights = int(density_weights)
+    c.flux = int(flux)
     return c
 
 
@@ -161,7 +164,7 @@ def config_for_workload(w, precision=None) -> rlb_config:
                        nu=w.nu, dt_over_dx=w.dt, tau=w.tau, eta_over_s=w.eta_over_s, alpha=w.alpha,
                        bc=w.bc, face_states=w.face_states, guard_umax=w.guard_umax,
                        guard_efloor=w.guard_efloor, lattice=w.lattice,
-                       density_weights=w.density_weights)
+                       density_weights=w.density_weights, flux=w.flux)
 
 
 def rlb_footprint_bytes(cfg: rlb_config) -> int:

@@ -34,8 +34,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layout_matches_header():
     from paper_1302_1125_amd import rlb
-    # sizeof(rlb_config) in C: 4 + 3*4 + 4*4 + 5*8 + 6*4 + 30*8 + 2*8 + 2*4
-    assert ctypes.sizeof(rlb.rlb_config) == 360
+    # sizeof(rlb_config) in C: 4 + 3*4 + 4*4 + 5*8 + 6*4 + 30*8 + 2*8 + 3*4,
+    # padded to a multiple of 8
+    assert ctypes.sizeof(rlb.rlb_config) == 368
     assert ctypes.sizeof(rlb.rlb_stats) == 64
     assert ctypes.sizeof(rlb.rlb_request) == 168
     assert ctypes.sizeof(rlb.rlb_server_stats) == 128
