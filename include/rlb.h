@@ -150,9 +150,12 @@ typedef struct {
                            equations, and in the Euler mode
                            (RLB_COLL_EULER) an admissible state stays
                            admissible (e.g. the gamma = 10 colliding slabs
-                           run without the guard).  The implicit update is
-                           not made admissible by it.  1D grids only
-                           (ny = nz = 1); not in the server.               */
+                           run without the guard; the convexity holds for
+                           dt/dx <= 1/(number of axes)).  The implicit update
+                           is not made admissible by it.  Extended lattice
+                           only; not in the server (1D grids run it in the
+                           blocked step, 2D and 3D grids in the staged step,
+                           not the z-march).                               */
 } rlb_config;
 
 typedef struct {

@@ -100,8 +100,8 @@ rlb_status validate(const rlb_config* c) {
       (c->lattice != RLB_LATTICE_EXTENDED || 13.0 / (c->nu * c->nu) < 17.0 / 24.0))
     return fail(RLB_E_INVALID_ARG, "isotropic density weights: extended lattice, nu <= 4.28");
   if (c->flux != RLB_FLUX_MINMOD && c->flux != RLB_FLUX_RUSANOV) return fail(RLB_E_INVALID_ARG, "flux");
-  if (c->flux == RLB_FLUX_RUSANOV && (c->lattice != RLB_LATTICE_EXTENDED || c->ny != 1 || c->nz != 1))
-    return fail(RLB_E_INVALID_ARG, "Rusanov flux: extended lattice, 1D grids (ny = nz = 1)");
+  if (c->flux == RLB_FLUX_RUSANOV && c->lattice != RLB_LATTICE_EXTENDED)
+    return fail(RLB_E_INVALID_ARG, "Rusanov flux: extended lattice only");
   if (c->tau_mode == RLB_TAU_UNIFORM && !(c->tau > 0 && std::isfinite(c->tau)))
     return fail(RLB_E_INVALID_ARG, "tau must be > 0");
   if (!(c->eta_over_s >= 0 && std::isfinite(c->eta_over_s))) return fail(RLB_E_INVALID_ARG, "eta_over_s >= 0");

@@ -53,7 +53,8 @@ inline long long population_stride(long long ncell) {
 constexpr long long kMaxCells = (1ll << 28) - 128;
 
 // Streaming flux of the extended model: the paper's minmod-limited upwind
-// flux, or the first-order Rusanov flux (beyond the paper; 1D, blocked step).
+// flux, or the first-order Rusanov flux (beyond the paper; k_step_tb in 1D,
+// the staged k_step in 2D and 3D).
 constexpr int kFluxMinmod = 0;
 constexpr int kFluxRusanov = 1;
 
@@ -113,7 +114,7 @@ struct StepParams {
   double tau;       // uniform relaxation time
   double nu2_etas;  // nu^2 * eta/s
   int tau_mode;     // 0 uniform, 1 eta/s
-  int flux;         // kFluxMinmod (Eqs. (47)-(53)) or kFluxRusanov (k_step_tb only)
+  int flux;         // kFluxMinmod (Eqs. (47)-(53)) or kFluxRusanov (not the z-march or segments)
   int guard;        // 0/1
   double m1, mmax, efloor;
   double gmax;      // Lorentz factor at m_max (bounds gamma of projected moments)

@@ -483,7 +483,7 @@ __device__ __forceinline__ void lds_barrier() {
 // Fill the LDS tiles of populations [S0, S1) (f in slots 0.., h after them):
 // halo loads first, then (after `sync_before`: the previous stage's reads are
 // done) the centre row, halo row and halo columns, then a barrier.
-template <typename T, int ACT, bool WH, int S0, int S1>
+template <typename T, int ACT, bool WH, int S0, int S1, bool RUS>
 __device__ __forceinline__ void stage_fill(T (*L)[kLH][kLW], const T* __restrict__ fin,
                                            const T* __restrict__ hin, long long S,
                                            const Nbr<ACT>& N, const T* fc, const T* hc,
@@ -497,23 +497,31 @@ __device__ __forceinline__ void stage_fill(T (*L)[kLH][kLW], const T* __restrict
   // has no x/y stencil).  Measured on MI355X: FP32 200 x 100 x 100 Euler step
   // 5% faster, 2048 x 1024 unchanged; FP64 384^3 2.7% slower, so FP64 tiles
   // load every row for every population.
+  // With the Rusanov flux (RUS) every population, f_0 and all of h included,
+  // reads one cell on each side along every axis: the inner rows only.
   constexpr bool by_sign = sizeof(T) == 4;
   auto load_rows = [&](auto sel) {
     static_for<0, NP>([&](auto k) {
       constexpr int I = S0 + k;
       constexpr int ey = (vcomp(I, 1) > 0) - (vcomp(I, 1) < 0);  // sign
-      if constexpr (I != 0 && halo_row_sel(sel, ey)) vr[k] = ldb(fin + I * S, N.hr);
-      if constexpr (WH && ey != 0 && halo_row_sel(sel, ey)) vrh[k] = ldb(hin + I * S, N.hr);
+      if constexpr (RUS || (I != 0 && halo_row_sel(sel, ey))) vr[k] = ldb(fin + I * S, N.hr);
+      if constexpr (WH && (RUS || (ey != 0 && halo_row_sel(sel, ey)))) vrh[k] = ldb(hin + I * S, N.hr);
     });
   };
-  if (!by_sign || w == 1 || w == 2) load_rows(std::integral_constant<int, 0>{});
-  else if (w == 0) load_rows(std::integral_constant<int, 1>{});
-  else load_rows(std::integral_constant<int, -1>{});
+  if constexpr (RUS) {
+    if (w == 1 || w == 2) load_rows(std::integral_constant<int, 0>{});
+  } else if (!by_sign || w == 1 || w == 2) {
+    load_rows(std::integral_constant<int, 0>{});
+  } else if (w == 0) {
+    load_rows(std::integral_constant<int, 1>{});
+  } else {
+    load_rows(std::integral_constant<int, -1>{});
+  }
   if (lane < 4) {
     static_for<0, NP>([&](auto k) {
       constexpr int I = S0 + k;
       vx[k] = ldb(fin + I * S, N.hx);
-      if constexpr (WH && vcomp(I, 0) != 0) vxh[k] = ldb(hin + I * S, N.hx);
+      if constexpr (WH && (RUS || vcomp(I, 0) != 0)) vxh[k] = ldb(hin + I * S, N.hx);
     });
   }
   if (sync_before) lds_barrier();
@@ -522,24 +530,30 @@ __device__ __forceinline__ void stage_fill(T (*L)[kLH][kLW], const T* __restrict
   static_for<0, NP>([&](auto k) {
     constexpr int I = S0 + k;
     L[k][2 + w][2 + lane] = fc[I];
-    if constexpr (WH && (vcomp(I, 0) != 0 || vcomp(I, 1) != 0)) L[NP + k][2 + w][2 + lane] = hc[I];
+    if constexpr (WH && (RUS || vcomp(I, 0) != 0 || vcomp(I, 1) != 0)) L[NP + k][2 + w][2 + lane] = hc[I];
   });
   auto store_rows = [&](auto sel) {
     static_for<0, NP>([&](auto k) {
       constexpr int I = S0 + k;
       constexpr int ey = (vcomp(I, 1) > 0) - (vcomp(I, 1) < 0);  // sign
-      if constexpr (I != 0 && halo_row_sel(sel, ey)) L[k][hrow][2 + lane] = vr[k];
-      if constexpr (WH && ey != 0 && halo_row_sel(sel, ey)) L[NP + k][hrow][2 + lane] = vrh[k];
+      if constexpr (RUS || (I != 0 && halo_row_sel(sel, ey))) L[k][hrow][2 + lane] = vr[k];
+      if constexpr (WH && (RUS || (ey != 0 && halo_row_sel(sel, ey)))) L[NP + k][hrow][2 + lane] = vrh[k];
     });
   };
-  if (!by_sign || w == 1 || w == 2) store_rows(std::integral_constant<int, 0>{});
-  else if (w == 0) store_rows(std::integral_constant<int, 1>{});
-  else store_rows(std::integral_constant<int, -1>{});
+  if constexpr (RUS) {
+    if (w == 1 || w == 2) store_rows(std::integral_constant<int, 0>{});
+  } else if (!by_sign || w == 1 || w == 2) {
+    store_rows(std::integral_constant<int, 0>{});
+  } else if (w == 0) {
+    store_rows(std::integral_constant<int, 1>{});
+  } else {
+    store_rows(std::integral_constant<int, -1>{});
+  }
   if (lane < 4) {
     static_for<0, NP>([&](auto k) {
       constexpr int I = S0 + k;
       L[k][2 + w][hcol] = vx[k];
-      if constexpr (WH && vcomp(I, 0) != 0) L[NP + k][2 + w][hcol] = vxh[k];
+      if constexpr (WH && (RUS || vcomp(I, 0) != 0)) L[NP + k][2 + w][hcol] = vxh[k];
     });
   }
   lds_barrier();
@@ -576,11 +590,23 @@ __device__ __forceinline__ void gather(const T* __restrict__ arr, const Nbr<ACT>
 
 // Stencil of population I of a staged tile: x and y from the LDS tile L
 // (this lane at row 2 + wavefront, column 2 + lane), z from the array.
-template <typename T, int ACT, int I, bool LAP>
+template <typename T, int ACT, int I, bool LAP, bool RUS>
 __device__ __forceinline__ void gather_lds(const T (*L)[kLW], const T* __restrict__ arr,
                                            const Nbr<ACT>& N, Sten<T>& s) {
   const int r = 2 + (static_cast<int>(threadIdx.x) >> 6);
   const int c = 2 + static_cast<int>(__lane_id());
+  if constexpr (RUS) {
+    // the Rusanov flux: one cell on each side along every axis (v[a][0], v[a][1])
+    s.v[0][0] = L[r][c - 1];
+    s.v[0][1] = L[r][c + 1];
+    s.v[1][0] = L[r - 1][c];
+    s.v[1][1] = L[r + 1][c];
+    if constexpr (axis_on<ACT>(2)) {
+      s.v[2][0] = ldb(arr, N.o[2][1]);
+      s.v[2][1] = ldb(arr, N.o[2][2]);
+    }
+    return;
+  }
   constexpr int ex = vcomp(I, 0), ey = vcomp(I, 1);
   if constexpr (ex > 0) {
     s.v[0][0] = L[r][c - 2];
@@ -625,8 +651,25 @@ __device__ __forceinline__ void gather_lds(const T (*L)[kLW], const T* __restric
 
 // delta t * (flux divergence) and the sum of the axis neighbours used by the
 // Laplacian (without the -2 f(x) per axis) of population I from its stencil.
-template <typename T, int ACT, int I, bool LAP>
-__device__ __forceinline__ void stream_terms(const Sten<T>& s, T c0, T dtv, T& dD, T& nsum) {
+template <typename T, int ACT, int I, bool LAP, bool RUS = false>
+__device__ __forceinline__ void stream_terms(const Sten<T>& s, T c0, T dtv, T& dD, T& nsum,
+                                             T dtc = T(0)) {
+  if constexpr (RUS) {
+    // the Rusanov flux (rusanov_terms) summed over the active axes; the
+    // stencil holds the cells on each side (v[a][0], v[a][1]), dtc = dt times
+    // the speed of light
+    bool first = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (!axis_on<ACT>(a)) continue;
+      const T fm = s.v[a][0], fp = s.v[a][1];
+      const T d = T(0.5) * (dtv * T(vcomp(I, a))) * (fp - fm) - T(0.5) * dtc * ((fp - c0) - (c0 - fm));
+      dD = first ? d : dD + d;
+      nsum = first ? fm + fp : nsum + (fm + fp);
+      first = false;
+    }
+    return;
+  }
   bool first_d = true, first_n = true;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -805,7 +848,7 @@ struct Batch {
 // Fused step: moments -> FP64 recovery -> equilibria -> limited streaming,
 // bulk term and implicit collision (Eq. (57)) or Euler update -> guard.
 // ---------------------------------------------------------------------------
-template <typename T, int ACT, bool WH, bool EULER, bool SEG>
+template <typename T, int ACT, bool WH, bool EULER, bool SEG, bool RUS = false>
 __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
     const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ hin,
     T* __restrict__ hout, double* __restrict__ hist, const uint8_t* __restrict__ obst,
@@ -901,7 +944,9 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
   // LDS tiles of a stage (2D/3D)
   __shared__ T lds[ACT != 1 ? Stages<T, WH, ACT>::arrays : 1][kLH][kLW];
 
+  static_assert(!RUS || ACT != 1, "the 1D Rusanov flux is built in k_step_tb");
   const T dtv = static_cast<T>(P.dtv);
+  const T dtc = static_cast<T>(P.dtv * sqrt(27.0 / 13.0));  // dt times the speed of light
   constexpr T NA2 = T(2 * n_axes<ACT>());
   // the stencils of a batch of populations (f and h) are gathered first so
   // that their loads are in flight together
@@ -917,11 +962,12 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
       static_for<0, NS>([&](auto st) {
         constexpr int S0 = st * PP;
         constexpr int S1 = S0 + PP < Q ? S0 + PP : Q;
-        stage_fill<T, ACT, WH, S0, S1>(lds, fin, hin, S, N, fc, hc, st > 0);
+        stage_fill<T, ACT, WH, S0, S1, RUS>(lds, fin, hin, S, N, fc, hc, st > 0);
         static_for<S0, S1>([&](auto I) {
           Sten<T> sf, sh;
-          gather_lds<T, ACT, I, (I != 0)>(lds[I - S0], fin + I * S, N, sf);
-          if constexpr (WH) gather_lds<T, ACT, I, false>(lds[(S1 - S0) + (I - S0)], hin + I * S, N, sh);
+          gather_lds<T, ACT, I, (I != 0), RUS>(lds[I - S0], fin + I * S, N, sf);
+          if constexpr (WH)
+            gather_lds<T, ACT, I, false, RUS>(lds[(S1 - S0) + (I - S0)], hin + I * S, N, sh);
           per_pop(I, sf, sh);
         });
       });
@@ -954,7 +1000,7 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
     stream_all([&](auto I, const Sten<T>& sfI, const Sten<T>& shI) {
       constexpr Vel e = vel(I);
       T dD, ns;
-      stream_terms<T, ACT, I, (I != 0)>(sfI, fc[I], dtv, dD, ns);
+      stream_terms<T, ACT, I, (I != 0), RUS>(sfI, fc[I], dtv, dD, ns, dtc);
       T v;
       if constexpr (I != 0) v = (fc[I] - dD) + kap * (ns - NA2 * fc[I]);
       else v = fc[I] - dD;
@@ -965,7 +1011,7 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
       if constexpr (e.z != 0) mz += double(e.z) * vd;
       if constexpr (WH) {
         T dH, nh;
-        stream_terms<T, ACT, I, false>(shI, hc[I], dtv, dH, nh);
+        stream_terms<T, ACT, I, false, RUS>(shI, hc[I], dtv, dH, nh, dtc);
         mh += static_cast<double>(hc[I] - dH);
         asm volatile("" : "+v"(mh));
       }
@@ -1101,7 +1147,7 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
     stream_all([&](auto I, const Sten<T>& sfI, const Sten<T>& shI) {
       constexpr Vel e = vel(I);
       T dD, ns;
-      stream_terms<T, ACT, I, (I != 0)>(sfI, fc[I], dtv, dD, ns);
+      stream_terms<T, ACT, I, (I != 0), RUS>(sfI, fc[I], dtv, dD, ns, dtc);
       T v = (fc[I] - dD) * tinv + static_cast<T>(weight(I)) * bracket<I>(Kt);
       if constexpr (I != 0) v += kinv * (ns - NA2 * fc[I]);
       stb_nt(fout + I * S, cbs, v);
@@ -1112,7 +1158,7 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
       if constexpr (e.z != 0) gZ += T(e.z) * v;
       if constexpr (WH) {
         T dH, nh;
-        stream_terms<T, ACT, I, false>(shI, hc[I], dtv, dH, nh);
+        stream_terms<T, ACT, I, false, RUS>(shI, hc[I], dtv, dH, nh, dtc);
         const T wpi = I == 0 ? wp[0] : (I <= 6 ? wp[1] : wp[2]);
         const T hv = (hc[I] - dH) * tinv + wpi * bracket<I>(Ht);
         stb_nt(hout + I * S, cbs, hv);
@@ -2266,6 +2312,18 @@ __global__ __launch_bounds__(kBlock) void k_sums_final(const double* partial, in
 
 template <typename T, int ACT, bool WH, bool EU>
 hipError_t launch_step_t(const StepParams& p, hipStream_t s) {
+  if (p.flux == kFluxRusanov) {
+    // the staged step (2D/3D); 1D grids take the blocked step (k_step_tb)
+    if constexpr (ACT == 1) {
+      return hipErrorInvalidValue;
+    } else {
+      const long long nblk = p.tiles_per_xcd * kXcds;
+      hipLaunchKernelGGL((k_step<T, ACT, WH, EU, false, true>), dim3(static_cast<unsigned>(nblk)), dim3(kBlock),
+                         0, s, static_cast<const T*>(p.f_in), static_cast<T*>(p.f_out),
+                         static_cast<const T*>(p.h_in), static_cast<T*>(p.h_out), p.hist, p.obst, p);
+      return hipGetLastError();
+    }
+  }
   if constexpr (ACT == 7 && !EU && std::is_same<T, float>::value) {
     if (p.zm_len > 0) {
       const long long nblk = p.zm_per_xcd * kXcds;

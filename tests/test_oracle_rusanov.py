@@ -48,6 +48,17 @@ def _ideal(eps, ux, uy, uz, n):
     return T, F, n * g, n * g * ux
 
 
+def _ideal_3d(eps, ux, uy, uz, n):
+    """T^{0 mu}, the fluxes T^{a mu} (a = x, y, z), N^0 and N^a of the ideal fluid."""
+    u = (ux, uy, uz)
+    g2 = 1.0 / (1.0 - (ux * ux + uy * uy + uz * uz))
+    T = np.array([eps * (4.0 * g2 - 1.0) / 3.0] + [4.0 / 3.0 * eps * g2 * v for v in u])
+    F = [np.array([T[1 + a]] + [4.0 / 3.0 * eps * g2 * u[a] * u[b] + (eps / 3.0 if a == b else 0.0)
+                                for b in range(3)]) for a in range(3)]
+    g = np.sqrt(g2)
+    return T, F, n * g, [n * g * v for v in u]
+
+
 def _rusanov(U, G, dt, s=1.0):
     r = lambda a, k: np.roll(a, -k, axis=-1)
     return U - dt * (0.5 * (r(G, 1) - r(G, -1)) - 0.5 * s * (r(U, 1) - 2.0 * U + r(U, -1)))
@@ -67,6 +78,37 @@ def test_euler_step_is_the_rusanov_scheme_of_the_fluid(umax):
     assert np.abs(N1 - _rusanov(N0, Nx, w.dt)).max() < 1e-13 * np.abs(N0).max()
     # the dissipation speed is the speed of light, not the axis speed sqrt(13/27)
     assert np.abs(T1 - _rusanov(T, F, w.dt, math.sqrt(13.0 / 27.0))).max() > 1e-4 * scale
+
+
+def test_euler_step_is_the_rusanov_scheme_in_3d():
+    """The same in 3D (periodic 7 x 6 x 5 grid, dt = 0.15): the update sums
+    the Rusanov differences of the three axes, each with the axis's flux."""
+    w = W.random_smooth_state(7, 6, 5, seed=13, with_density=True, alpha=0.0, tau_mode=W.TAU_UNIFORM,
+                              tau=1.0, dt=0.15, umax=0.5)
+    w = w.copy_with(collision=W.COLL_EULER, flux=W.FLUX_RUSANOV)
+    o = oracle_for(w)
+    T, F, N0, Nf = _ideal_3d(*w.fields())
+    assert o.step(1) == 0
+    T1, _, N1, _ = _ideal_3d(*o.fields())
+    dt = w.dt
+    Tp, Np = T.copy(), N0.copy()
+    for a, ax in enumerate((3, 2, 1)):  # x, y, z are the last three array axes of [mu][z][y][x]
+        r = lambda q, k, ax=ax: np.roll(q, -k, axis=ax)
+        rn = lambda q, k, ax=ax: np.roll(q, -k, axis=ax - 1)
+        Tp -= dt * (0.5 * (r(F[a], 1) - r(F[a], -1)) - 0.5 * (r(T, 1) - 2.0 * T + r(T, -1)))
+        Np -= dt * (0.5 * (rn(Nf[a], 1) - rn(Nf[a], -1)) - 0.5 * (rn(N0, 1) - 2.0 * N0 + rn(N0, -1)))
+    assert np.abs(T1 - Tp).max() < 1e-13 * np.abs(T).max()
+    assert np.abs(N1 - Np).max() < 1e-13 * np.abs(N0).max()
+
+
+def test_strong_3d_shock_cloud_stays_admissible():
+    """The paper's 3D shock-cloud in the strong regime (driver T0 = 54.77, Euler
+    mode, dt = 0.15, so dt s = 0.45 summed over the axes) at 40 x 20 x 20, 200
+    steps, guard off: admissible throughout with the Rusanov flux; the minmod
+    flux leaves the admissible set at step 20 of the same run."""
+    w = W.shock_cloud_3d(nx=40, ny=20, nz=20, regime="strong", precision=W.FP64, steps=200, guard_umax=0.0)
+    assert oracle_for(w.copy_with(flux=W.FLUX_RUSANOV)).step(200) == 0
+    assert 0 < oracle_for(w).step(200) <= 30
 
 
 @pytest.mark.parametrize("euler", [True, False])
