@@ -151,7 +151,9 @@ typedef struct {
                            (RLB_COLL_EULER) an admissible state stays
                            admissible (e.g. the gamma = 10 colliding slabs
                            run without the guard; the convexity holds for
-                           dt/dx <= 1/(number of axes)).  The implicit update
+                           dt/dx <= 1/(number of axes)).  With this flux the
+                           bulk term of Eq. (54) acts on the rest population
+                           too, so that it diffuses every moment alike.  The implicit update
                            is not made admissible by it.  Extended lattice
                            only; not in the server (1D grids run it in the
                            blocked step, 2D and 3D grids in the staged step,

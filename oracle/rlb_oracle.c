@@ -481,6 +481,18 @@ static inline double rusanov_div(double p, double s, double fm1, double f0,
   return 0.5 * p * (fp1 - fm1) - 0.5 * s * ((fp1 - f0) - (f0 - fm1));
 }
 
+/* Bulk-term coefficient lambda_i / (c_0 nu dt / c_t) of population i: alpha
+   for the moving populations, 0 for the rest population (Eq. (55)).  With the
+   Rusanov flux (beyond the paper) the rest population takes the bulk term too:
+   its weight is negative, and without it the term would move energy at a
+   cell by -kappa times the Laplacian of the rest population's energy, which
+   breaks the convexity that keeps that flux's moment update admissible; with
+   it the term is kappa times the Laplacian of every moment. */
+static inline double bulk_lambda(const orc_state* S, int i) {
+  if (i == 0 && S->cfg.flux != ORC_FLUX_RUSANOV) return 0.0;
+  return S->cfg.alpha;
+}
+
 /* Sum over axes of [h_i^a(x) - h_i^a(x - e_a)] / dx: the divergence of the
    limited flux of p_i^a f_i between the interfaces x +- 1/2 (Eq. (47),
    conservative reading), with p_i^a = xi_i^a; or of the Rusanov flux above
@@ -723,7 +735,7 @@ int64_t orc_step(orc_state* S, int64_t nsteps) {
         const long p = pidx(S, x, y, z);
         for (int i = 0; i < ORC_Q; ++i) {
           const double* fi = S->f + i * NP;
-          const double lam = (i == 0) ? 0.0 : S->cfg.alpha; /* Eq. (55) */
+          const double lam = bulk_lambda(S, i);
           const double B = c0_ct * nu * dt * lam * laplacian(S, fi, x, y, z);
           S->fs[i * NP + p] = fi[p] - c0_ct * dt * div_flux(S, fi, i, x, y, z) + B;
           if (with_h) {
@@ -776,7 +788,7 @@ int64_t orc_step(orc_state* S, int64_t nsteps) {
         double fnew[ORC_Q], hnew[ORC_Q];
         for (int i = 0; i < ORC_Q; ++i) {
           const double* fi = S->f + i * NP;
-          const double lam = (i == 0) ? 0.0 : S->cfg.alpha; /* Eq. (55) */
+          const double lam = bulk_lambda(S, i);
           const double B = c0_ct * nu * dt * lam * laplacian(S, fi, x, y, z);
           const double D = c0_ct * dt * div_flux(S, fi, i, x, y, z);
           fnew[i] = (fi[p] - D + omega * (2.0 * fe[i] - fe_prev[i]) + B) /

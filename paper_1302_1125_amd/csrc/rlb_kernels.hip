@@ -1002,7 +1002,7 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
       T dD, ns;
       stream_terms<T, ACT, I, (I != 0), RUS>(sfI, fc[I], dtv, dD, ns, dtc);
       T v;
-      if constexpr (I != 0) v = (fc[I] - dD) + kap * (ns - NA2 * fc[I]);
+      if constexpr (I != 0 || RUS) v = (fc[I] - dD) + kap * (ns - NA2 * fc[I]);
       else v = fc[I] - dD;
       const double vd = static_cast<double>(v);
       m0 += vd;
@@ -1149,7 +1149,7 @@ __global__ __launch_bounds__(kBlock, (Occ<T, ACT>::value)) void k_step(
       T dD, ns;
       stream_terms<T, ACT, I, (I != 0), RUS>(sfI, fc[I], dtv, dD, ns, dtc);
       T v = (fc[I] - dD) * tinv + static_cast<T>(weight(I)) * bracket<I>(Kt);
-      if constexpr (I != 0) v += kinv * (ns - NA2 * fc[I]);
+      if constexpr (I != 0 || RUS) v += kinv * (ns - NA2 * fc[I]);
       stb_nt(fout + I * S, cbs, v);
       gE += v;
       gA += fabs(v);
@@ -1768,7 +1768,10 @@ struct TbOcc {
 // light), so that the moments of the update are the Rusanov scheme of the
 // fluid equations.  cx = dt p (the population's Courant number along x),
 // cs = dt s.  dD: dt times the flux divergence; nsum: the Laplacian's
-// neighbour sum.
+// neighbour sum.  With this flux the bulk term acts on the rest population
+// too (its weight is negative; without it the term would remove the rest
+// population's energy at the cell and break the convexity that keeps the
+// moment update admissible).
 template <typename T>
 __device__ __forceinline__ void rusanov_terms(T fm, T f0, T fp, T cx, T cs, T& dD, T& nsum) {
   dD = T(0.5) * cx * (fp - fm) - T(0.5) * cs * ((fp - f0) - (f0 - fm));
@@ -1923,7 +1926,7 @@ __global__ __launch_bounds__(kBlock, (TbOcc<T>::value)) void k_step_tb(
           stream_terms<T, 1, I, (I != 0)>(sf, fc[I], dtv, dD, ns);
         }
         T v;
-        if constexpr (I != 0) v = (fc[I] - dD) + kap * (ns - NA2 * fc[I]);
+        if constexpr (I != 0 || RUS) v = (fc[I] - dD) + kap * (ns - NA2 * fc[I]);
         else v = fc[I] - dD;
         const double vd = static_cast<double>(v);
         m0 += vd;
@@ -2014,7 +2017,7 @@ __global__ __launch_bounds__(kBlock, (TbOcc<T>::value)) void k_step_tb(
           stream_terms<T, 1, I, (I != 0)>(sf, fc[I], dtv, dD, ns);
         }
         T v = (fc[I] - dD) * tinv + static_cast<T>(weight(I)) * bracket<I>(Kt);
-        if constexpr (I != 0) v += kinv * (ns - NA2 * fc[I]);
+        if constexpr (I != 0 || RUS) v += kinv * (ns - NA2 * fc[I]);
         fc[I] = v;
         gE += v;
         gA += fabs(v);

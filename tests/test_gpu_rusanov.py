@@ -169,14 +169,15 @@ def test_strong_3d_shock_cloud_parity_without_guard(rlb):
 
 @pytest.mark.parametrize("precision", [W.FP64, W.MIXED])
 def test_strong_3d_shock_cloud_full_size(rlb, precision):
-    """200 x 100 x 100, 1000 steps, guard off, bulk term off: admissible
-    throughout with the Rusanov flux in FP64 and mixed precision.  The
-    recipe's bulk term (alpha = 0.2) acts on the moving populations only, so
-    at the cell it removes energy carried by the rest population, whose
-    weight is negative; the update is then no longer a convex combination of
-    admissible states, and this run leaves the admissible set (step 359 in
-    FP64 on the GPU, 357 in the oracle; step 262 in mixed precision)."""
-    w = W.shock_cloud_3d(regime="strong", precision=precision, guard_umax=0.0, alpha=0.0)
+    """200 x 100 x 100, 1000 steps, the recipe's bulk term (alpha = 0.2), guard
+    off: admissible throughout with the Rusanov flux in FP64 and mixed
+    precision.  Under this flux the bulk term acts on the rest population too;
+    when it acted on the moving populations only (as Eq. (55) has it), it
+    removed the rest population's (negative-weight) energy at the cell, the
+    update was no longer a convex combination of admissible states, and this
+    run left the admissible set at step 359 in FP64 (357 in the oracle) and
+    262 in mixed precision."""
+    w = W.shock_cloud_3d(regime="strong", precision=precision, guard_umax=0.0)
     w = w.copy_with(flux=W.FLUX_RUSANOV)
     out, st = _gpu(rlb, w, w.steps, precision)
     assert st.first_bad_step == -1 and st.guard_events == 0

@@ -64,9 +64,17 @@ def _rusanov(U, G, dt, s=1.0):
     return U - dt * (0.5 * (r(G, 1) - r(G, -1)) - 0.5 * s * (r(U, 1) - 2.0 * U + r(U, -1)))
 
 
-@pytest.mark.parametrize("umax", [0.3, 0.8])
-def test_euler_step_is_the_rusanov_scheme_of_the_fluid(umax):
-    w = W.random_smooth_state(40, 1, 1, seed=11, with_density=True, alpha=0.0, tau_mode=W.TAU_UNIFORM,
+def _lap(U, ax=-1):
+    return np.roll(U, -1, axis=ax) - 2.0 * U + np.roll(U, 1, axis=ax)
+
+
+@pytest.mark.parametrize("umax,alpha", [(0.3, 0.0), (0.8, 0.0), (0.8, 0.2)])
+def test_euler_step_is_the_rusanov_scheme_of_the_fluid(umax, alpha):
+    """With the bulk term (alpha > 0) the update adds kappa times the
+    Laplacian of every T^{0 mu}, kappa = (nu^2 / sqrt 27) alpha dt: the rest
+    population takes the term too under this flux (without it T^{00} would
+    differ by kappa times the Laplacian of the rest population's energy)."""
+    w = W.random_smooth_state(40, 1, 1, seed=11, with_density=True, alpha=alpha, tau_mode=W.TAU_UNIFORM,
                               tau=1.0, dt=0.25, umax=umax)
     w = w.copy_with(collision=W.COLL_EULER, flux=W.FLUX_RUSANOV)
     o = oracle_for(w)
@@ -74,16 +82,18 @@ def test_euler_step_is_the_rusanov_scheme_of_the_fluid(umax):
     assert o.step(1) == 0
     T1, _, N1, _ = _ideal(*[a.ravel() for a in o.fields()])
     scale = np.abs(T).max()
-    assert np.abs(T1 - _rusanov(T, F, w.dt)).max() < 1e-13 * scale
+    kappa = w.nu ** 2 / math.sqrt(27.0) * alpha * w.dt
+    assert np.abs(T1 - (_rusanov(T, F, w.dt) + kappa * _lap(T))).max() < 1e-13 * scale
     assert np.abs(N1 - _rusanov(N0, Nx, w.dt)).max() < 1e-13 * np.abs(N0).max()
     # the dissipation speed is the speed of light, not the axis speed sqrt(13/27)
     assert np.abs(T1 - _rusanov(T, F, w.dt, math.sqrt(13.0 / 27.0))).max() > 1e-4 * scale
 
 
 def test_euler_step_is_the_rusanov_scheme_in_3d():
-    """The same in 3D (periodic 7 x 6 x 5 grid, dt = 0.15): the update sums
-    the Rusanov differences of the three axes, each with the axis's flux."""
-    w = W.random_smooth_state(7, 6, 5, seed=13, with_density=True, alpha=0.0, tau_mode=W.TAU_UNIFORM,
+    """The same in 3D (periodic 7 x 6 x 5 grid, dt = 0.15, alpha = 0.2): the
+    update sums the Rusanov differences of the three axes, each with the
+    axis's flux, and the bulk term of each axis."""
+    w = W.random_smooth_state(7, 6, 5, seed=13, with_density=True, alpha=0.2, tau_mode=W.TAU_UNIFORM,
                               tau=1.0, dt=0.15, umax=0.5)
     w = w.copy_with(collision=W.COLL_EULER, flux=W.FLUX_RUSANOV)
     o = oracle_for(w)
@@ -96,6 +106,7 @@ def test_euler_step_is_the_rusanov_scheme_in_3d():
         r = lambda q, k, ax=ax: np.roll(q, -k, axis=ax)
         rn = lambda q, k, ax=ax: np.roll(q, -k, axis=ax - 1)
         Tp -= dt * (0.5 * (r(F[a], 1) - r(F[a], -1)) - 0.5 * (r(T, 1) - 2.0 * T + r(T, -1)))
+        Tp += w.nu ** 2 / math.sqrt(27.0) * w.alpha * dt * (r(T, 1) - 2.0 * T + r(T, -1))
         Np -= dt * (0.5 * (rn(Nf[a], 1) - rn(Nf[a], -1)) - 0.5 * (rn(N0, 1) - 2.0 * N0 + rn(N0, -1)))
     assert np.abs(T1 - Tp).max() < 1e-13 * np.abs(T).max()
     assert np.abs(N1 - Np).max() < 1e-13 * np.abs(N0).max()
