@@ -244,8 +244,9 @@ rlb_status rlb_moments_noalloc(rlb_ctx* ctx, double* eps, double* ux, double* uy
 
 /* Steps one kernel launch advances: 1 for 2D/3D grids and the basic
    lattice; for 1D grids of the extended lattice the temporal-blocking depth
-   (default 8, at most 16; the RLB_TB_STEPS environment variable read at
-   rlb_create overrides it, 1 = one step per launch).  A launch then reads and
+   (default 16 when nx <= 192 x the device's compute-unit count, so that each
+   workgroup has a CU of its own, else 8; the RLB_TB_STEPS environment
+   variable read at rlb_create overrides it, 1..16, 1 = one step per launch).  A launch then reads and
    writes every cell's state once for that many steps.  0 if ctx is NULL. */
 int32_t rlb_steps_per_launch(const rlb_ctx* ctx);
 

@@ -431,6 +431,14 @@ rlb_status rlb_create(const rlb_config* cfg, void* hip_stream, rlb_ctx** out) {
   if (const char* e = std::getenv("RLB_TB_STEPS")) {  // tuning override, 1 = off
     const int v = std::atoi(e);
     x->tb_steps = v < 1 ? 1 : (v > rlb::kTbMaxSteps ? rlb::kTbMaxSteps : v);
+  } else if (x->act_mask == 1) {
+    // a 1D grid that gives every workgroup a CU of its own even at 16 steps
+    // per launch leaves CUs idle anyway: the wider recomputed overlap then
+    // costs no wall time and the launches halve (on MI355X 6.9% more
+    // cell-updates per second at 1000 cells, 5.6% at 8192)
+    const int kb = rlb::kTbMaxSteps;
+    const long long tiles = (cfg->nx + rlb::tb_cells_per_tile(kb) - 1) / rlb::tb_cells_per_tile(kb);
+    if (tiles <= prop.multiProcessorCount) x->tb_steps = kb;
   }
   if (hip_stream) {
     x->stream = static_cast<hipStream_t>(hip_stream);

@@ -157,11 +157,31 @@ def test_tb_mixed_tube_against_oracle(rlb):
     assert errs["eps"] <= 2e-5 and errs["n"] <= 2e-5 and errs["gux"] <= 2e-4, errs
 
 
+@pytest.mark.parametrize("precision", [W.FP64, W.MIXED])
+def test_blocking_depth_does_not_change_results(rlb, precision):
+    """A step's arithmetic does not depend on how many steps one launch
+    takes: 8 and 16 steps per launch (and a ragged last launch of 5) give the
+    same fields bit for bit, on fixed/outflow and periodic ends."""
+    for nx, bc in ((1000, (1, 2)), (777, (0, 0))):
+        w = _smooth_1d(nx, 3 + nx, bc)
+        a, sa, _ = _run(rlb, w, 69, 8, precision=precision)
+        b, sb, _ = _run(rlb, w, 69, 16, precision=precision)
+        assert sa.guard_events == sb.guard_events
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), (nx, precision)
+
+
 def test_steps_per_launch(rlb):
-    w1 = W.shock_tube_1d()
-    ctx = rlb.context_for_workload(w1)
-    assert ctx.rlb_steps_per_launch() == 8
-    ctx.close()
+    """16 steps per launch where even that grid gives every workgroup a CU
+    of its own, 8 on longer 1D domains, one step elsewhere."""
+    import torch
+    assert "RLB_TB_STEPS" not in os.environ
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    per16 = 256 - 4 * 16  # cells one workgroup owns at 16 steps per launch
+    for nx, want in ((1000, 16), (cus * per16, 16), (cus * per16 + 1, 8)):
+        ctx = rlb.context_for_workload(W.shock_tube_1d(nx=nx))
+        assert ctx.rlb_steps_per_launch() == want, (nx, cus)
+        ctx.close()
     w3 = W.random_smooth_state(8, 8, 8, seed=1)
     ctx = rlb.context_for_workload(w3)
     assert ctx.rlb_steps_per_launch() == 1
