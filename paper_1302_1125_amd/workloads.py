@@ -200,25 +200,27 @@ def shock_cloud_2d(nx=2048, ny=1024, steps=20000, gamma_s=3.0, cloud_radius=96.0
 
 def blast_wave_3d(n=384, steps=2000, radius=32.0, energy_ratio=1e3, eta_over_s=0.02,
                   alpha=0.2, precision=MIXED, seed=SEED_BASE + 5, nu=NU_DEFAULT,
-                  dt=0.15, guard_umax=0.999) -> Workload:
+                  dt=0.15, guard_umax=0.999, nz=None) -> Workload:
     """Workload 5: periodic cube with an overpressure sphere of radius 32
     cells (energy ratio 1e3) at the centre of a medium with seeded 1%
     log-normal density fluctuations n = exp(0.01 g - 0.5e-4), g ~ N(0,1).
     The radius scales with n / 384.  The admissibility guard is on by
     default (the density distribution turns inadmissible at the blast front
-    within a few tens of steps without it)."""
+    within a few tens of steps without it).  nz (default n) makes the box
+    n x n x nz with the sphere at its centre."""
+    nz = n if nz is None else nz
     rng = np.random.default_rng(seed)
-    shape = (n, n, n)
+    shape = (nz, n, n)
     g = rng.standard_normal(shape, dtype=np.float64)
     dens = np.exp(0.01 * g - 0.5e-4)
     del g
-    c = n / 2.0
     r = radius * n / 384.0
-    ax = np.arange(n) + 0.5 - c
-    d2 = ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2
+    ax = np.arange(n) + 0.5 - n / 2.0
+    az = np.arange(nz) + 0.5 - nz / 2.0
+    d2 = az[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2
     eps = np.where(d2 < r * r, 3.0 * energy_ratio, 3.0)
     del d2
-    w = Workload("blast_wave_3d", n, n, n, steps, precision=precision,
+    w = Workload("blast_wave_3d", n, n, nz, steps, precision=precision,
                  tau_mode=TAU_ETA_OVER_S, eta_over_s=eta_over_s, alpha=alpha,
                  with_density=True, nu=nu, dt=dt, bc=[BC_PERIODIC] * 6,
                  guard_umax=guard_umax)

@@ -103,3 +103,34 @@ def test_shock_cloud_3d_200x100x100_mixed(rlb, regime):
 @pytest.mark.parametrize("regime", ["weak", "strong"])
 def test_shock_cloud_3d_200x100x100_fp64(rlb, regime):
     _compare(rlb, W.shock_cloud_3d(regime=regime, precision=W.FP64), W.FP64, FP64_TOL)
+
+
+@pytest.mark.parametrize("nz", [728, 729])
+def test_blast_wave_at_the_zmarch_size_limit(rlb, nz):
+    """384 x 384 x nz blast wave, mixed precision.  The z-marching step
+    addresses the 10 (or 9) population arrays of a descriptor group by
+    32-bit byte offsets, so it takes grids whose population stride stays
+    below 2^32 / 40 - 64 elements: 728 planes (stride 107 348 032) is the
+    largest such 384 x 384 grid and runs on it, with a ragged last run of 8
+    planes; 729 planes (107 495 488) take the one-thread-per-cell step.  The
+    sampled cells: the far corner (the largest byte offsets, its crop wraps
+    around the periodic faces), a cell of the last run at the y = 0 face,
+    and a cell at the edge of the overpressure sphere."""
+    w = W.blast_wave_3d(precision=W.MIXED, nz=nz)
+    n = w.nx
+    cells = [(nz - 1, n - 1, n - 1), (nz - 5, 0, 100), (nz // 2, n // 2, n // 2 + 31)]
+    print(f"[gpu-case] z-march size limit: 384x384x{nz}, {len(cells)} oracle cells", flush=True)
+    ref = sampled_oracle_fields(w, cells, STEPS)
+    ctx = rlb.context_for_workload(w, precision=W.MIXED)
+    ctx.rlb_step(STEPS)
+    g = ctx.rlb_moments()
+    ctx.close()
+    got = np.array([[float(a[c]) for a in g] for c in cells])
+    del g
+    scale = np.maximum(np.abs(ref), 1e-300)
+    scale[:, 1:4] = 1.0
+    worst = (np.abs(got - ref) / scale).max(axis=0)
+    print("max rel. error per field (eps, ux, uy, uz, n):", worst)
+    assert np.all(np.isfinite(got))
+    for k, name in enumerate(("eps", "ux", "uy", "uz", "n")):
+        assert worst[k] <= MIXED_TOL[name], (name, worst[k])
