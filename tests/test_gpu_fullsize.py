@@ -134,3 +134,37 @@ def test_blast_wave_at_the_zmarch_size_limit(rlb, nz):
     assert np.all(np.isfinite(got))
     for k, name in enumerate(("eps", "ux", "uy", "uz", "n")):
         assert worst[k] <= MIXED_TOL[name], (name, worst[k])
+
+
+@pytest.mark.parametrize("dims", ["1d", "3d"])
+def test_largest_grid_fp64(rlb, dims):
+    """Grids of the largest accepted size in FP64, where the 32-bit byte
+    offsets of the FP64 arrays come closest to 2^31 (2^28 - 128 stored cells;
+    one more is rejected, tests/test_abi.py): a 1D shock tube of 2^28 - 128
+    cells (the temporally blocked step, 1.2 M workgroups per launch) and a
+    640 x 640 x 655 blast wave with density (268 288 000 cells, 162 GiB of
+    device memory).  The first and last cells (the largest offsets, their
+    crops reach the fixed or wrapped faces) and a cell where the initial
+    state jumps are recomputed by the oracle; rel. error <= 1e-10."""
+    limit = (1 << 28) - 128
+    if dims == "1d":
+        w = W.shock_tube_1d(nx=limit)
+        cells = [(0, 0, 0), (0, 0, limit - 1), (0, 0, limit // 2)]
+    else:
+        w = W.blast_wave_3d(n=640, nz=limit // (640 * 640), precision=W.FP64)
+        nz, n = w.nz, w.nx
+        cells = [(0, 0, 0), (nz - 1, n - 1, n - 1), (nz // 2, n // 2, n // 2 + 53)]
+    print(f"[gpu-case] largest grid {dims}: {w.nx}x{w.ny}x{w.nz} FP64, {len(cells)} oracle cells", flush=True)
+    ref = sampled_oracle_fields(w, cells, STEPS)
+    ctx = rlb.context_for_workload(w, precision=W.FP64)
+    ctx.rlb_step(STEPS)
+    g = ctx.rlb_moments()
+    ctx.close()
+    got = np.array([[float(a[c]) for a in g] for c in cells])
+    del g
+    scale = np.maximum(np.abs(ref), 1e-300)
+    scale[:, 1:4] = 1.0
+    worst = (np.abs(got - ref) / scale).max(axis=0)
+    print("max rel. error per field (eps, ux, uy, uz, n):", worst)
+    assert np.all(np.isfinite(got))
+    assert worst.max() <= 1e-10, worst
