@@ -1356,10 +1356,10 @@ constexpr int kNT = RLB_STREAMING ? 2 : 0;
 #endif
 // 1: the outer halo rows of a z-marching tile are loaded only for the sign
 // of e^y that reads them (0: every row for every population).  Measured on
-// MI355X at 384^3: 5.6% slower (the branches raise register spills from 13 to
-// 22 values), so off.
+// MI355X at 384^3 with the centres staged through LDS (RLB_ZM_CENLDS): 1%
+// faster (3 spilled values); with the centres in registers 5.6% slower (22).
 #ifndef RLB_ZM_ROWS
-#define RLB_ZM_ROWS 0
+#define RLB_ZM_ROWS 1
 #endif
 // wave priority while a z-marching wave issues a burst of loads (0: off);
 // measured on MI355X: 0.6% faster at 384^3
@@ -1368,6 +1368,13 @@ constexpr int kNT = RLB_STREAMING ? 2 : 0;
 #endif
 // populations staged through LDS together (f and h) in the z-marching step
 constexpr int kZmPops = (Q + RLB_ZM_STAGES - 1) / RLB_ZM_STAGES;
+// 1: the next plane's centres without a window and previous-step fields are
+// loaded straight into LDS (double-buffered per wavefront) instead of
+// registers, which frees 15 registers across the recovery and the streaming
+// phase (spills 13 -> 3 values; alone no faster, but room for RLB_ZM_ROWS)
+#ifndef RLB_ZM_CENLDS
+#define RLB_ZM_CENLDS 1
+#endif
 
 template <typename T, bool WH>
 __global__ __launch_bounds__(kBlock, RLB_ZM_OCC) void k_step_zm(
@@ -1451,10 +1458,45 @@ __global__ __launch_bounds__(kBlock, RLB_ZM_OCC) void k_step_zm(
     else return ho[ho_index(i)];
   };
   // centres without a z window and the previous-step fields of a plane
-  // (loaded one plane ahead)
+  // (loaded one plane ahead, into LDS or these registers)
   T f0n;
   T hon[WH ? 9 : 1];
   float qn[5];
+#if RLB_ZM_CENLDS
+  // per wavefront and plane parity: f_0, the 9 centres of h without a
+  // window, the 5 previous-step fields (64 lanes each)
+  __shared__ float cen[2][kTY][15][64];
+  auto dma = [&](__amdgpu_buffer_rsrc_t r, int slot, int zq, unsigned voff, unsigned soff, auto aux) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+        r, (__attribute__((address_space(3))) void*)(&cen[zq & 1][wv][slot][0]), 4, voff, soff, 0,
+        decltype(aux)::value);
+  };
+  auto load_centres = [&](int zq) {
+    const unsigned c = cxy + static_cast<unsigned>(zq) * cst;
+    const unsigned oq = inside ? sxy + static_cast<unsigned>(zq) * plane_bytes : 0u;
+    static_for<0, 5>([&](auto k) {
+      dma(Qh.g[0], 10 + k, zq, oq, static_cast<unsigned>(k) * qb, std::integral_constant<int, kNT>{});
+    });
+    dma(Fi.g[0], 0, zq, c, 0u, std::integral_constant<int, 0>{});
+    if constexpr (WH) {
+      static_for<0, Q>([&](auto I) {
+        constexpr int i = I;
+        if constexpr (ho_index(i) >= 0)
+          dma(Hi.g[zm_grp(i)], 1 + ho_index(i), zq, c, static_cast<unsigned>(i - zm_grp_first(zm_grp(i))) * sb,
+              std::integral_constant<int, 0>{});
+      });
+    }
+  };
+  auto read_centres = [&](int zq) {
+    f0n = cen[zq & 1][wv][0][lane];
+    if constexpr (WH) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) hon[k] = cen[zq & 1][wv][1 + k][lane];
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) qn[k] = cen[zq & 1][wv][10 + k][lane];
+  };
+#else
   auto load_centres = [&](int zq) {
     const unsigned c = cxy + static_cast<unsigned>(zq) * cst;
     const unsigned oq = inside ? sxy + static_cast<unsigned>(zq) * plane_bytes : 0u;
@@ -1467,6 +1509,8 @@ __global__ __launch_bounds__(kBlock, RLB_ZM_OCC) void k_step_zm(
       });
     }
   };
+  auto read_centres = [&](int) {};
+#endif
   // first planes of the run
   {
     load_centres(zb);
@@ -1492,6 +1536,7 @@ __global__ __launch_bounds__(kBlock, RLB_ZM_OCC) void k_step_zm(
     const unsigned pz = static_cast<unsigned>(z) * plane_bytes;
     const unsigned cl = cxy + static_cast<unsigned>(z) * cst;  // this lane's value at z
     const unsigned cbs = sxy + pz;                             // its storage cell
+    read_centres(z);  // from LDS (RLB_ZM_CENLDS); the loads' wait is the compiler's
     f0c = f0n;
     if constexpr (WH) {
 #pragma unroll
